@@ -1,0 +1,178 @@
+/* atns.h - C ABI of the MI355X Asynchrony-Tolerant (AT) compressible Navier-Stokes library.
+ *
+ * Method: Kumari & Donzis, "Direct Numerical Simulations of turbulent flows using high-order
+ * Asynchrony-Tolerant schemes: accuracy and performance".  The library evaluates the right-hand
+ * side of the compressible Navier-Stokes equations (Sec. 2, Eqs. cont, mome, ie, written in
+ * total-energy flux form) on the triply periodic box [0, 2 pi)^3 with 4th-order central first
+ * derivatives, replacing every stencil point that lies across a face of a processing element
+ * (PE) by the AT combination of that face's past published levels (Sec. 2.1, Eq. at; Appendix B,
+ * Table atschemes, (1,4) rows), and advances it with a low-storage third-order Runge-Kutta step.
+ * The PEs of the paper's domain decomposition (Sec. 3, Eqs. NT, NI, NB) are virtual here: they
+ * tile one GPU's grid, each publishes the two layers next to each of its six faces into a
+ * device-resident ring of time levels (the send buffers of Sec. 3.1), and a delay schedule
+ * (Sec. 3.1.1 Alg. SAA, Sec. 3.1.2 Alg. CAA) says which level each face reads at each step.
+ *
+ * Conventions for every call:
+ *   - Return value: AT_OK (0) or a negative at_status; no exception crosses the ABI.
+ *     at_last_error() gives a message for the calling thread's last failure.
+ *   - Fields are structure-of-arrays, index order [component][z][y][x], x fastest.  Conserved
+ *     components: 0 rho, 1 rho u, 2 rho v, 3 rho w, 4 E = rho (c_v T + |u|^2 / 2).
+ *   - Host arrays passed in are read during the call only and never retained.
+ *   - The device workspace and the HIP stream belong to the caller, who keeps both alive until
+ *     at_destroy; the library never frees them.  The library itself allocates (hipMalloc) only the
+ *     delay table, the forcing table and a small staging buffer, and frees them in at_destroy.
+ *   - All device work is enqueued on the caller's stream; calls returning host data
+ *     (at_stats, at_get_field) synchronise that stream.  One host thread per handle.
+ *   - NaN / Inf in the state is reported through at_stats.nonfinite, not as an error.
+ */
+#ifndef ATNS_H
+#define ATNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ATNS_API __attribute__((visibility("default")))
+
+/* Opaque handle of one simulation (state, ring, schedule) bound to one device and stream. */
+typedef struct at_sim at_sim;
+
+typedef enum at_status {
+  AT_OK = 0,
+  AT_E_INVAL = -1,      /* bad argument, shape, divisibility or physical parameter          */
+  AT_E_WORKSPACE = -2,  /* workspace pointer NULL / misaligned or smaller than required     */
+  AT_E_SCHEDULE = -3,   /* delay > max_delay, a read of a level never published, or a step  */
+                        /* beyond the schedule / forcing table                               */
+  AT_E_HIP = -4,        /* a HIP runtime call failed (message in at_last_error)             */
+  AT_E_STATE = -5       /* call out of order (e.g. stepping before at_init_field)           */
+} at_status;
+
+typedef enum at_precision { AT_FP64 = 0, AT_FP32 = 1 } at_precision;
+
+/* Delay modes (Sec. 3.1).  SYNC: every face reads the current level.  CAA (Alg. CAA): PEs
+ * exchange every c_r steps, so from step c_r on the delay is n mod c_r on every face, with
+ * L = c_r - 1.  SAA (Alg. SAA): one exchange per step, delays random and bounded by L; from
+ * step L + 3 on each (step, PE, face) delay is an independent uniform draw in {0..L} made with
+ * SplitMix64 (Steele, Lea & Flood, 2014): z = output number ((n P + t) 6 + f) + 1 of the
+ * generator seeded with `seed`, k = ((z >> 32) (L + 1)) >> 32.  EXPLICIT: a caller table. */
+typedef enum at_delay_mode { AT_SYNC = 0, AT_CAA = 1, AT_SAA = 2, AT_EXPLICIT = 3 } at_delay_mode;
+
+typedef struct at_config {
+  int32_t n[3];        /* grid points in x, y, z; h_d = 2 pi / n[d]                            */
+  int32_t p[3];        /* virtual PEs per direction; n[d] % p[d] == 0 and n[d] / p[d] >= 4      */
+  int32_t order;       /* spatial order; 4 is the only value accepted                           */
+  int32_t max_delay;   /* largest delay any face may use (0..8); the ring keeps max_delay + 3   */
+                       /* levels (L + t_l levels per PE, Sec. 3.1)                              */
+  int32_t precision;   /* AT_FP64 or AT_FP32 (fields, fluxes, ring and stencils); reductions of */
+                       /* statistics and of the conserved totals are FP64 in both modes         */
+  int32_t forcing;     /* 0: unforced; 1: add rho f to momentum and rho f.u to energy, with f   */
+                       /* from at_set_forcing (Sec. 4.2)                                        */
+  double gamma;        /* ratio of specific heats (1.4)                                          */
+  double prandtl;      /* Prandtl number; conductivity k = mu c_p / Pr (0.7)                    */
+  double gas_r;        /* gas constant R; p = rho R T, c_v = R / (gamma - 1) (1.0)              */
+  double mu_ref;       /* viscosity mu = mu_ref (T / t_ref)^mu_exp                               */
+  double t_ref;        /* reference temperature of the viscosity law (1.0)                      */
+  double mu_exp;       /* viscosity exponent (0.76)                                              */
+  double dt;           /* fixed time step (Sec. 2.2: no CFL reduction inside the step loop)     */
+} at_config;
+
+typedef struct at_stats_s {
+  int64_t step;        /* steps taken since the first supplied level                           */
+  double time;         /* step * dt                                                             */
+  double mass, mom[3], energy;           /* FP64 sums of the current field times h^3          */
+  double mass_rk, mom_rk[3], energy_rk;  /* initial totals plus the FP64 sum over all RK     */
+                                         /* stages of B_s * sum(dQ) * h^3                     */
+  double K;            /* <rho |u|^2 / 2>                                 (Sec. 4.1)            */
+  double eps;          /* <sigma_ij du_i/dx_j>, mean viscous dissipation  (Sec. 4.1)            */
+  double enstrophy;    /* <|curl u|^2>                                    (Sec. 4.1)            */
+  double Mt;           /* <|u|^2>^{1/2} / (gamma R <T>)^{1/2}             (Sec. 4, set-up)      */
+  double umax;         /* max over points of |u|                                                */
+  int32_t nonfinite;   /* 1 if any conserved value is NaN or Inf                                */
+  int32_t reserved;
+} at_stats_t;
+
+/* Library version string. */
+ATNS_API const char* at_version(void);
+
+/* Message for the calling thread's last failing call ("" if none). */
+ATNS_API const char* at_last_error(void);
+
+/* Bytes of device workspace at_create needs for `cfg` (0 if cfg is invalid).  Holds the
+ * conserved state, the RK register, derivative and flux scratch, and the ring of published face
+ * layers: (max_delay + 3) levels x 9 components (u, v, w, T and the face-normal flux of the five
+ * conserved variables) x 4 (1/ex + 1/ey + 1/ez) N^3 points. */
+ATNS_API size_t at_workspace_bytes(const at_config* cfg);
+
+/* Create a simulation handle.  dev_workspace: device memory of at least at_workspace_bytes(cfg)
+ * bytes, 256-byte aligned, owned by the caller.  hip_stream: a hipStream_t (NULL = default
+ * stream) on the current device.  Errors: AT_E_INVAL (config), AT_E_WORKSPACE (size/alignment),
+ * AT_E_HIP. */
+ATNS_API int at_create(const at_config* cfg, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                       at_sim** out);
+
+/* Load the state.  q_host: host float64 [n_levels][5][nz][ny][nx], oldest level first; the last
+ * level becomes the current state Q^{n0}, n0 = n_levels - 1, and the older ones are published as
+ * levels 0 .. n0 - 1 with synchronous derivatives (the synchronous start-up loop of Algs. SAA and
+ * CAA fills L + t_l levels).  1 <= n_levels <= max_delay + 3.  Resets the step counter to n0, the
+ * RK register and the conserved-total accumulators.  Errors: AT_E_INVAL, AT_E_HIP. */
+ATNS_API int at_init_field(at_sim* sim, const double* q_host, int32_t n_levels);
+
+/* Set the delay schedule for absolute steps 0 .. n_steps-1 (see at_delay_mode).  L and c_r are
+ * used by CAA (L must equal c_r - 1) and SAA; seed by SAA; table (host int8
+ * [n_steps][p_x p_y p_z][6], PE index (tz p_y + ty) p_x + tx, faces -x,+x,-y,+y,-z,+z) by
+ * EXPLICIT only (NULL otherwise).  Every entry must satisfy 0 <= k <= max_delay and, if k > 0,
+ * n - k - 2 >= 0.  Errors: AT_E_INVAL, AT_E_SCHEDULE (entry invalid), AT_E_HIP. */
+ATNS_API int at_set_delay_schedule(at_sim* sim, int32_t mode, int32_t L, int32_t c_r,
+                                   uint64_t seed, const int8_t* table, int64_t n_steps);
+
+/* Forcing amplitudes for absolute steps 0 .. n_steps-1: host float64 [n_steps][40][3][2]
+ * (re, im).  The 40 wavevectors are the half space (kz > 0, or kz = 0 and ky > 0, or
+ * kz = ky = 0 and kx > 0) of the integer k with 0 < |k|^2 <= 6, ordered by kz, then ky, then kx
+ * ascending; f(x) = sum_k 2 Re(fhat_k exp(i k.x)), held fixed within a step.  Errors: AT_E_INVAL
+ * (forcing disabled in the config, bad sizes), AT_E_HIP. */
+ATNS_API int at_set_forcing(at_sim* sim, const double* fhat_host, int64_t n_steps);
+
+/* RHS at the current state and step with that step's delays at stage time c = 0, without
+ * publishing or changing the state.  dev_out: device [5][nz][ny][nx] in the config's precision.
+ * Errors: AT_E_STATE, AT_E_SCHEDULE, AT_E_HIP. */
+ATNS_API int at_rhs(at_sim* sim, void* dev_out);
+
+/* Enqueue n_steps full steps of Williamson's low-storage RK3 (A = 0, -5/9, -153/128;
+ * B = 1/3, 15/16, 8/15; c = 0, 1/3, 3/4).  Stage 1 of step n publishes level n.  A delayed face
+ * (k >= 1) at stage s extrapolates levels n-k, n-k-1, n-k-2 to t_n + c_s dt with weights
+ * w_0 = (kappa+1)(kappa+2)/2, w_1 = -kappa(kappa+2), w_2 = kappa(kappa+1)/2, kappa = k + c_s
+ * (the Appendix B polynomials at c_s = 0); k = 0 reads the neighbour's current stage.
+ * Asynchronous: returns after enqueueing.  Errors: AT_E_STATE, AT_E_SCHEDULE, AT_E_HIP. */
+ATNS_API int at_rk_step(at_sim* sim, int32_t n_steps);
+
+/* Statistics of the current state (synchronous derivatives on the whole periodic grid; global
+ * reductions are the only all-PE operations, as in Sec. 3.1) into *out.  Synchronises the stream.
+ * Errors: AT_E_STATE, AT_E_HIP. */
+ATNS_API int at_stats(at_sim* sim, at_stats_t* out);
+
+/* Copy the current conserved state to host float64 [5][nz][ny][nx].  Synchronises the stream. */
+ATNS_API int at_get_field(at_sim* sim, double* q_host);
+
+/* Device pointer to the current conserved state (config precision, [5][nz][ny][nx]); valid until
+ * the next call on the handle.  Errors: AT_E_STATE. */
+ATNS_API int at_field_device(at_sim* sim, void** dev_ptr);
+
+/* Kernel timing.  While enabled, every kernel the handle launches is bracketed by two HIP events
+ * recorded on the handle's stream; at_kernel_timing synchronises the stream and returns, for kernel
+ * `kernel` (0 .. AT_N_KERNELS-1, named by at_kernel_name), the summed event time in ms and the
+ * number of launches since timing was enabled.  Errors: AT_E_INVAL, AT_E_HIP. */
+#define AT_N_KERNELS 6
+ATNS_API int at_set_kernel_timing(at_sim* sim, int32_t enable);
+ATNS_API int at_kernel_timing(at_sim* sim, int32_t kernel, double* total_ms, int64_t* launches);
+ATNS_API const char* at_kernel_name(int32_t kernel);
+
+/* Release the handle and the library's own allocations (not the workspace or stream). */
+ATNS_API int at_destroy(at_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ATNS_H */

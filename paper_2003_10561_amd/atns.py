@@ -1,0 +1,232 @@
+"""Python binding of libatns (include/atns.h): argument marshalling only.
+
+Every step of the method runs in the gfx950 kernels of libatns.so; this module allocates the
+workspace with torch on the current CUDA (HIP) device, passes torch's current stream, and converts
+arguments.  There is no CPU fallback: importing it without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libatns.so")
+
+AT_OK, AT_E_INVAL, AT_E_WORKSPACE, AT_E_SCHEDULE, AT_E_HIP, AT_E_STATE = 0, -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+SYNC, CAA, SAA, EXPLICIT = 0, 1, 2, 3
+N_FORCE = 40
+EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "at_init_field",
+            "at_set_delay_schedule", "at_set_forcing", "at_rhs", "at_rk_step", "at_stats",
+            "at_get_field", "at_field_device", "at_destroy", "at_set_kernel_timing",
+            "at_kernel_timing", "at_kernel_name"]
+N_KERNELS = 6
+
+
+class AtError(RuntimeError):
+    def __init__(self, call: str, rc: int, msg: str):
+        super().__init__(f"{call} failed ({rc}): {msg}")
+        self.rc = rc
+
+
+class _Config(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("p", C.c_int32 * 3), ("order", C.c_int32),
+                ("max_delay", C.c_int32), ("precision", C.c_int32), ("forcing", C.c_int32),
+                ("gamma", C.c_double), ("prandtl", C.c_double), ("gas_r", C.c_double),
+                ("mu_ref", C.c_double), ("t_ref", C.c_double), ("mu_exp", C.c_double),
+                ("dt", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("step", C.c_int64), ("time", C.c_double), ("mass", C.c_double),
+                ("mom", C.c_double * 3), ("energy", C.c_double), ("mass_rk", C.c_double),
+                ("mom_rk", C.c_double * 3), ("energy_rk", C.c_double), ("K", C.c_double),
+                ("eps", C.c_double), ("enstrophy", C.c_double), ("Mt", C.c_double),
+                ("umax", C.c_double), ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libatns.so and declare its signatures.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libatns.so not built at {path}; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.at_version.restype = C.c_char_p
+    lib.at_last_error.restype = C.c_char_p
+    lib.at_workspace_bytes.argtypes = [C.POINTER(_Config)]
+    lib.at_workspace_bytes.restype = C.c_size_t
+    lib.at_create.argtypes = [C.POINTER(_Config), vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.at_init_field.argtypes = [vp, dp, i32]
+    lib.at_set_delay_schedule.argtypes = [vp, i32, i32, i32, C.c_uint64, C.POINTER(C.c_int8), i64]
+    lib.at_set_forcing.argtypes = [vp, dp, i64]
+    lib.at_rhs.argtypes = [vp, vp]
+    lib.at_rk_step.argtypes = [vp, i32]
+    lib.at_stats.argtypes = [vp, C.POINTER(_Stats)]
+    lib.at_get_field.argtypes = [vp, dp]
+    lib.at_field_device.argtypes = [vp, C.POINTER(vp)]
+    lib.at_destroy.argtypes = [vp]
+    lib.at_set_kernel_timing.argtypes = [vp, i32]
+    lib.at_kernel_timing.argtypes = [vp, i32, dp, C.POINTER(C.c_int64)]
+    lib.at_kernel_name.argtypes = [i32]
+    lib.at_kernel_name.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(call, rc):
+    if rc != AT_OK:
+        raise AtError(call, rc, load_library().at_last_error().decode())
+
+
+@dataclass
+class Config:
+    n: tuple
+    p: tuple
+    dt: float
+    mu_ref: float
+    max_delay: int = 3
+    precision: str = "fp64"
+    forcing: bool = False
+    gamma: float = 1.4
+    prandtl: float = 0.7
+    gas_r: float = 1.0
+    t_ref: float = 1.0
+    mu_exp: float = 0.76
+    order: int = 4
+
+    def to_c(self) -> _Config:
+        c = _Config()
+        for d in range(3):
+            c.n[d] = int(self.n[d])
+            c.p[d] = int(self.p[d])
+        c.order = int(self.order)
+        c.max_delay = int(self.max_delay)
+        c.precision = FP32 if self.precision == "fp32" else FP64
+        c.forcing = int(bool(self.forcing))
+        for k in ("gamma", "prandtl", "gas_r", "mu_ref", "t_ref", "mu_exp", "dt"):
+            setattr(c, k, float(getattr(self, k)))
+        return c
+
+    @property
+    def shape(self):
+        return (int(self.n[2]), int(self.n[1]), int(self.n[0]))
+
+    @property
+    def ntiles(self):
+        return int(self.p[0] * self.p[1] * self.p[2])
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float32 if self.precision == "fp32" else torch.float64
+
+
+def workspace_bytes(cfg: Config) -> int:
+    c = cfg.to_c()
+    return int(load_library().at_workspace_bytes(C.byref(c)))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Sim:
+    """One simulation on the current device: workspace (torch-owned) + handle."""
+
+    def __init__(self, cfg: Config, device=None, stream=None):
+        import torch
+        self.lib = load_library()
+        self.cfg = cfg
+        self._c = cfg.to_c()
+        nbytes = int(self.lib.at_workspace_bytes(C.byref(self._c)))
+        if nbytes == 0:
+            raise AtError("at_workspace_bytes", AT_E_INVAL, self.lib.at_last_error().decode())
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check("at_create", self.lib.at_create(C.byref(self._c), C.c_void_p(self.workspace.data_ptr()),
+                                               nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.at_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_field(self, q: np.ndarray, n_levels: int = 1):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        _check("at_init_field", self.lib.at_init_field(self.h, _dp(q), int(n_levels)))
+
+    def set_delay_schedule(self, mode, L=0, c_r=1, seed=0, table=None, n_steps=None):
+        tp = None
+        if table is not None:
+            table = np.ascontiguousarray(table, dtype=np.int8)
+            if n_steps is None:
+                n_steps = table.shape[0]
+            tp = table.ctypes.data_as(C.POINTER(C.c_int8))
+        _check("at_set_delay_schedule", self.lib.at_set_delay_schedule(
+            self.h, int(mode), int(L), int(c_r), C.c_uint64(seed), tp, int(n_steps)))
+
+    def set_forcing(self, fhat: np.ndarray):
+        fhat = np.ascontiguousarray(fhat, dtype=np.float64)
+        assert fhat.shape[1:] == (N_FORCE, 3, 2)
+        _check("at_set_forcing", self.lib.at_set_forcing(self.h, _dp(fhat), fhat.shape[0]))
+
+    def rhs(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((5,) + self.cfg.shape, dtype=self.cfg.torch_dtype, device=self.device)
+        assert out.is_contiguous() and out.dtype == self.cfg.torch_dtype
+        _check("at_rhs", self.lib.at_rhs(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def rk_step(self, n_steps: int = 1):
+        _check("at_rk_step", self.lib.at_rk_step(self.h, int(n_steps)))
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check("at_stats", self.lib.at_stats(self.h, C.byref(s)))
+        return {"step": s.step, "time": s.time, "mass": s.mass, "momx": s.mom[0], "momy": s.mom[1],
+                "momz": s.mom[2], "energy": s.energy, "mass_rk": s.mass_rk, "momx_rk": s.mom_rk[0],
+                "momy_rk": s.mom_rk[1], "momz_rk": s.mom_rk[2], "energy_rk": s.energy_rk, "K": s.K,
+                "eps": s.eps, "enstrophy": s.enstrophy, "Mt": s.Mt, "umax": s.umax,
+                "nonfinite": s.nonfinite}
+
+    def get_field(self) -> np.ndarray:
+        out = np.empty((5,) + self.cfg.shape, dtype=np.float64)
+        _check("at_get_field", self.lib.at_get_field(self.h, _dp(out)))
+        return out
+
+    def set_kernel_timing(self, enable: bool):
+        _check("at_set_kernel_timing", self.lib.at_set_kernel_timing(self.h, int(bool(enable))))
+
+    def kernel_timing(self) -> dict:
+        """{kernel name: (total ms, launches)} for kernels launched since timing was enabled."""
+        out = {}
+        for k in range(N_KERNELS):
+            ms, cnt = C.c_double(), C.c_int64()
+            _check("at_kernel_timing", self.lib.at_kernel_timing(self.h, k, C.byref(ms), C.byref(cnt)))
+            if cnt.value:
+                out[self.lib.at_kernel_name(k).decode()] = (ms.value, cnt.value)
+        return out
+
+    def field_device_ptr(self) -> int:
+        p = C.c_void_p()
+        _check("at_field_device", self.lib.at_field_device(self.h, C.byref(p)))
+        return int(p.value)

@@ -1,0 +1,623 @@
+// Host side of the C ABI (include/atns.h): validation, workspace layout, schedules, forcing
+// tables, and the stage loop of the low-storage RK3 step.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "atns_internal.h"
+
+using namespace atns;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(AT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Williamson (1980) low-storage RK3 coefficients.
+constexpr double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+constexpr double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+constexpr double kRkC[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t q, dq, grad, flux, ring, tot_part, stat_part, stat_out, force_table, phase_x, phase_y,
+      phase_z, total;
+};
+
+int validate(const at_config* c) {
+  if (!c) return fail(AT_E_INVAL, "config is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (c->n[d] < 4 || c->p[d] < 1) return fail(AT_E_INVAL, "n[d] >= 4 and p[d] >= 1 required");
+    if (c->n[d] % c->p[d]) return fail(AT_E_INVAL, "n[d] must be a multiple of p[d]");
+    if (c->n[d] / c->p[d] < 4) return fail(AT_E_INVAL, "PE edge n[d]/p[d] must be >= 4");
+    if (c->n[d] > (1 << 14)) return fail(AT_E_INVAL, "n[d] too large");
+  }
+  if (c->order != 4) return fail(AT_E_INVAL, "only order 4 is implemented");
+  if (c->max_delay < 0 || c->max_delay > kMaxDelay) return fail(AT_E_INVAL, "max_delay out of 0..8");
+  if (c->precision != AT_FP64 && c->precision != AT_FP32) return fail(AT_E_INVAL, "bad precision");
+  if (c->forcing != 0 && c->forcing != 1) return fail(AT_E_INVAL, "forcing must be 0 or 1");
+  if (!(c->gamma > 1.0) || !(c->gas_r > 0.0) || !(c->prandtl > 0.0) || !(c->t_ref > 0.0) ||
+      !(c->mu_ref >= 0.0) || !(c->dt > 0.0) || !std::isfinite(c->mu_exp))
+    return fail(AT_E_INVAL, "bad physical parameter");
+  return AT_OK;
+}
+
+Geom make_geom(const at_config* c) {
+  Geom g{};
+  g.npts = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = c->n[d];
+    g.p[d] = c->p[d];
+    g.e[d] = c->n[d] / c->p[d];
+    g.npts *= c->n[d];
+  }
+  g.slab[0] = (int64_t)4 * c->p[0] * c->n[1] * c->n[2];
+  g.slab[1] = (int64_t)4 * c->p[1] * c->n[0] * c->n[2];
+  g.slab[2] = (int64_t)4 * c->p[2] * c->n[0] * c->n[1];
+  g.ring_dir_off[0] = 0;
+  g.ring_dir_off[1] = kNRing * g.slab[0];
+  g.ring_dir_off[2] = kNRing * (g.slab[0] + g.slab[1]);
+  g.ring_slot = kNRing * (g.slab[0] + g.slab[1] + g.slab[2]);
+  g.R = c->max_delay + 3;
+  g.ntiles = c->p[0] * c->p[1] * c->p[2];
+  return g;
+}
+
+Layout make_layout(const at_config* c, const Geom& g) {
+  const size_t w = c->precision == AT_FP32 ? 4 : 8;
+  const size_t N = (size_t)g.npts;
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.q = take(kNQ * N * w);
+  L.dq = take(kNQ * N * w);
+  L.grad = take(kNGrad * N * w);
+  L.flux = take(3 * kNQ * N * w);
+  L.ring = take((size_t)g.R * g.ring_slot * w);
+  L.tot_part = take((size_t)update_blocks(g) * kNQ * 8);
+  L.stat_part = take((size_t)stats_blocks(g) * kNStat * 8);
+  L.stat_out = take(32 * 8);
+  L.force_table = take((size_t)kMaxPairs * c->n[0] * 6 * w);
+  L.phase_x = take((size_t)5 * c->n[0] * 2 * w);
+  L.phase_y = take((size_t)5 * c->n[1] * 2 * w);
+  L.phase_z = take((size_t)3 * c->n[2] * 2 * w);
+  L.total = off;
+  return L;
+}
+
+// HIP events around each launch; pairs are harvested when timings are queried.
+struct EventTimer final : LaunchHook {
+  struct Pending {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  hipEvent_t open_ev = nullptr;
+  double total_ms[kKCount] = {};
+  int64_t launches[kKCount] = {};
+  bool failed = false;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) failed = true;
+    return e;
+  }
+  void before(int, hipStream_t s) override {
+    open_ev = get();
+    if (open_ev && hipEventRecord(open_ev, s) != hipSuccess) failed = true;
+  }
+  void after(int id, hipStream_t s) override {
+    hipEvent_t e = get();
+    if (e && hipEventRecord(e, s) != hipSuccess) failed = true;
+    pending.push_back({id, open_ev, e});
+    open_ev = nullptr;
+  }
+  hipError_t harvest(hipStream_t s) {
+    hipError_t err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return err;
+    for (const Pending& p : pending) {
+      float ms = 0.f;
+      if (p.a && p.b && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        total_ms[p.id] += ms;
+        launches[p.id] += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+    return hipSuccess;
+  }
+  void reset() {
+    for (int i = 0; i < kKCount; ++i) {
+      total_ms[i] = 0.0;
+      launches[i] = 0;
+    }
+  }
+  ~EventTimer() override {
+    for (hipEvent_t e : pool)
+      if (e) (void)hipEventDestroy(e);
+    for (const Pending& p : pending) {
+      if (p.a) (void)hipEventDestroy(p.a);
+      if (p.b) (void)hipEventDestroy(p.b);
+    }
+  }
+};
+
+}  // namespace
+
+struct at_sim {
+  at_config cfg;
+  Geom g;
+  Layout L;
+  hipStream_t stream;
+  int device;
+  uint8_t* ws;
+  int8_t* d_sched = nullptr;
+  int64_t sched_steps = 0;
+  int8_t* d_zero = nullptr;
+  double* d_fhat = nullptr;
+  int64_t force_steps = 0;
+  int* d_wv = nullptr;  // [2][40]: kx, pair id
+  int npair = 0;
+  int pair_ky[kMaxPairs], pair_kz[kMaxPairs];
+  double* d_staging = nullptr;  // 5 N doubles
+  int64_t step = 0;
+  int initialised = 0;
+  double tot_init[kNQ];
+  EventTimer* timer = nullptr;  // non-null while kernel timing is enabled
+};
+
+namespace {
+
+template <typename T>
+Coef<T> make_coef(const at_sim* s) {
+  Coef<T> cf{};
+  for (int d = 0; d < 3; ++d) cf.inv12h[d] = (T)(1.0 / (12.0 * (kTwoPi / s->cfg.n[d])));
+  const double cv = s->cfg.gas_r / (s->cfg.gamma - 1.0);
+  const double cp = s->cfg.gamma * s->cfg.gas_r / (s->cfg.gamma - 1.0);
+  cf.gas_r = (T)s->cfg.gas_r;
+  cf.inv_cv = (T)(1.0 / cv);
+  cf.cp_over_pr = (T)(cp / s->cfg.prandtl);
+  cf.mu_ref = (T)s->cfg.mu_ref;
+  cf.inv_tref = (T)(1.0 / s->cfg.t_ref);
+  cf.mu_exp = (T)s->cfg.mu_exp;
+  return cf;
+}
+
+template <typename T>
+StageArgs<T> base_args(at_sim* s) {
+  StageArgs<T> a{};
+  a.g = s->g;
+  a.cf = make_coef<T>(s);
+  a.q = (T*)(s->ws + s->L.q);
+  a.dq = (T*)(s->ws + s->L.dq);
+  a.grad = (T*)(s->ws + s->L.grad);
+  a.flux = (T*)(s->ws + s->L.flux);
+  a.ring = (T*)(s->ws + s->L.ring);
+  a.tot_part = (double*)(s->ws + s->L.tot_part);
+  a.vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
+  a.dt = (T)s->cfg.dt;
+  a.force.table = nullptr;
+  a.force.phase_y = (const T*)(s->ws + s->L.phase_y);
+  a.force.phase_z = (const T*)(s->ws + s->L.phase_z);
+  a.force.npair = s->npair;
+  for (int i = 0; i < kMaxPairs; ++i) {
+    a.force.pair_ky[i] = s->pair_ky[i];
+    a.force.pair_kz[i] = s->pair_kz[i];
+  }
+  return a;
+}
+
+// Forcing wavevectors in the documented order, and the (ky, kz) pair of each.
+void forcing_lists(int kx[kNForce], int pair[kNForce], int pky[kMaxPairs], int pkz[kMaxPairs],
+                   int* npair) {
+  int nk = 0, np = 0;
+  for (int kz = -2; kz <= 2; ++kz)
+    for (int ky = -2; ky <= 2; ++ky)
+      for (int x = -2; x <= 2; ++x) {
+        const int k2 = x * x + ky * ky + kz * kz;
+        if (k2 == 0 || k2 > 6) continue;
+        if (!(kz > 0 || (kz == 0 && ky > 0) || (kz == 0 && ky == 0 && x > 0))) continue;
+        int pid = -1;
+        for (int j = 0; j < np; ++j)
+          if (pky[j] == ky && pkz[j] == kz) pid = j;
+        if (pid < 0) {
+          pid = np++;
+          pky[pid] = ky;
+          pkz[pid] = kz;
+        }
+        kx[nk] = x;
+        pair[nk] = pid;
+        ++nk;
+      }
+  *npair = np;
+}
+
+template <typename T>
+int upload_phases(at_sim* s) {
+  auto table = [&](int n, int m0, int nm, size_t off) -> int {
+    std::vector<T> h((size_t)nm * n * 2);
+    for (int m = 0; m < nm; ++m)
+      for (int j = 0; j < n; ++j) {
+        const double ph = (double)(m0 + m) * kTwoPi * j / n;
+        h[((size_t)m * n + j) * 2] = (T)std::cos(ph);
+        h[((size_t)m * n + j) * 2 + 1] = (T)std::sin(ph);
+      }
+    HIP_TRY(hipMemcpyAsync(s->ws + off, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return AT_OK;
+  };
+  int rc = table(s->cfg.n[0], -2, 5, s->L.phase_x);
+  if (!rc) rc = table(s->cfg.n[1], -2, 5, s->L.phase_y);
+  if (!rc) rc = table(s->cfg.n[2], 0, 3, s->L.phase_z);
+  return rc;
+}
+
+uint64_t splitmix64(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+int do_stats(at_sim* s, double* host_out) {
+  const Coef<T> cf = make_coef<T>(s);
+  double* part = (double*)(s->ws + s->L.stat_part);
+  double* out = (double*)(s->ws + s->L.stat_out);
+  HIP_TRY(launch_stats<T>(s->g, cf, (const T*)(s->ws + s->L.q), part, out,
+                          (const double*)(s->ws + s->L.tot_part), update_blocks(s->g), s->cfg.gamma,
+                          s->stream, s->timer));
+  HIP_TRY(hipMemcpyAsync(host_out, out, (kNStat + kNQ) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return AT_OK;
+}
+
+template <typename T>
+int do_init(at_sim* s, const double* q_host, int nlev) {
+  const int64_t N = s->g.npts;
+  T* q = (T*)(s->ws + s->L.q);
+  for (int lev = 0; lev < nlev; ++lev) {
+    HIP_TRY(hipMemcpyAsync(s->d_staging, q_host + (size_t)lev * kNQ * N, sizeof(double) * kNQ * N,
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(launch_convert<T>(s->d_staging, q, kNQ * N, s->stream));
+    if (lev < nlev - 1) {
+      StageArgs<T> a = base_args<T>(s);
+      a.delays = s->d_zero;
+      a.step = lev;
+      a.cstage = T(0);
+      a.publish = 1;
+      HIP_TRY(launch_publish_history<T>(a, s->stream));
+    }
+  }
+  HIP_TRY(hipMemsetAsync(s->ws + s->L.dq, 0, sizeof(T) * kNQ * N, s->stream));
+  HIP_TRY(hipMemsetAsync(s->ws + s->L.tot_part, 0, sizeof(double) * kNQ * update_blocks(s->g), s->stream));
+  double st[kNStat + kNQ];
+  int rc = do_stats<T>(s, st);
+  if (rc) return rc;
+  const double vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
+  for (int c = 0; c < kNQ; ++c) s->tot_init[c] = st[c] * vol;
+  s->step = nlev - 1;
+  s->initialised = 1;
+  return AT_OK;
+}
+
+int check_step_tables(at_sim* s, int64_t first, int64_t count) {
+  if (!s->d_sched || first + count > s->sched_steps)
+    return fail(AT_E_SCHEDULE, "delay schedule does not cover the requested steps");
+  if (s->cfg.forcing && (!s->d_fhat || first + count > s->force_steps))
+    return fail(AT_E_SCHEDULE, "forcing table does not cover the requested steps");
+  return AT_OK;
+}
+
+template <typename T>
+int do_steps(at_sim* s, int nsteps) {
+  const size_t row = (size_t)s->g.ntiles * 6;
+  for (int it = 0; it < nsteps; ++it) {
+    StageArgs<T> a = base_args<T>(s);
+    a.delays = s->d_sched + (size_t)s->step * row;
+    a.step = s->step;
+    if (s->cfg.forcing) {
+      T* tab = (T*)(s->ws + s->L.force_table);
+      HIP_TRY(launch_force_table<T>(s->g, s->d_fhat + (size_t)s->step * kNForce * 6, s->d_wv,
+                                    s->d_wv + kNForce, s->npair, tab,
+                                    (const T*)(s->ws + s->L.phase_x), s->stream, s->timer));
+      a.force.table = tab;
+    }
+    for (int st = 0; st < 3; ++st) {
+      a.cstage = (T)kRkC[st];
+      a.rk_a = (T)kRkA[st];
+      a.rk_b = (T)kRkB[st];
+      a.publish = st == 0;
+      HIP_TRY(launch_stage<T>(a, s->stream, s->timer));
+    }
+    s->step++;
+  }
+  return AT_OK;
+}
+
+template <typename T>
+int do_rhs(at_sim* s, void* out) {
+  StageArgs<T> a = base_args<T>(s);
+  a.delays = s->d_sched + (size_t)s->step * s->g.ntiles * 6;
+  a.step = s->step;
+  a.cstage = T(0);
+  a.rk_a = T(0);
+  a.rk_b = T(0);
+  a.publish = 0;
+  a.rhs_out = (T*)out;
+  if (s->cfg.forcing) {
+    T* tab = (T*)(s->ws + s->L.force_table);
+    HIP_TRY(launch_force_table<T>(s->g, s->d_fhat + (size_t)s->step * kNForce * 6, s->d_wv,
+                                  s->d_wv + kNForce, s->npair, tab, (const T*)(s->ws + s->L.phase_x),
+                                  s->stream, s->timer));
+    a.force.table = tab;
+  }
+  HIP_TRY(launch_stage<T>(a, s->stream, s->timer));
+  return AT_OK;
+}
+
+template <typename T>
+int do_get_field(at_sim* s, double* q_host) {
+  const int64_t N = s->g.npts;
+  HIP_TRY(launch_to_double<T>((const T*)(s->ws + s->L.q), s->d_staging, kNQ * N, s->stream));
+  HIP_TRY(hipMemcpyAsync(q_host, s->d_staging, sizeof(double) * kNQ * N, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return AT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* at_version(void) { return "atns 0.1 (gfx950)"; }
+
+const char* at_last_error(void) { return g_last_error.c_str(); }
+
+size_t at_workspace_bytes(const at_config* cfg) {
+  if (validate(cfg)) return 0;
+  const Geom g = make_geom(cfg);
+  return make_layout(cfg, g).total;
+}
+
+int at_create(const at_config* cfg, void* ws, size_t ws_bytes, void* stream, at_sim** out) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!out) return fail(AT_E_INVAL, "out is NULL");
+  const Geom g = make_geom(cfg);
+  const Layout L = make_layout(cfg, g);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(AT_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(AT_E_WORKSPACE, "workspace smaller than at_workspace_bytes");
+  at_sim* s = new (std::nothrow) at_sim();
+  if (!s) return fail(AT_E_INVAL, "out of host memory");
+  s->cfg = *cfg;
+  s->g = g;
+  s->L = L;
+  s->stream = (hipStream_t)stream;
+  s->ws = (uint8_t*)ws;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e == hipSuccess) e = hipMalloc(&s->d_zero, (size_t)g.ntiles * 6);
+  if (e == hipSuccess) e = hipMemsetAsync(s->d_zero, 0, (size_t)g.ntiles * 6, s->stream);
+  if (e == hipSuccess) e = hipMalloc(&s->d_staging, sizeof(double) * kNQ * g.npts);
+  if (e == hipSuccess) e = hipMalloc(&s->d_wv, sizeof(int) * 2 * kNForce);
+  if (e != hipSuccess) {
+    at_destroy(s);
+    return fail(AT_E_HIP, std::string("allocation: ") + hipGetErrorString(e));
+  }
+  int wv[2 * kNForce];
+  forcing_lists(wv, wv + kNForce, s->pair_ky, s->pair_kz, &s->npair);
+  e = hipMemcpyAsync(s->d_wv, wv, sizeof(wv), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    at_destroy(s);
+    return fail(AT_E_HIP, std::string("upload: ") + hipGetErrorString(e));
+  }
+  rc = cfg->precision == AT_FP32 ? upload_phases<float>(s) : upload_phases<double>(s);
+  if (rc) {
+    at_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return AT_OK;
+}
+
+int at_init_field(at_sim* s, const double* q_host, int32_t n_levels) {
+  if (!s || !q_host) return fail(AT_E_INVAL, "NULL argument");
+  if (n_levels < 1 || n_levels > s->g.R) return fail(AT_E_INVAL, "n_levels must be in 1 .. max_delay + 3");
+  return s->cfg.precision == AT_FP32 ? do_init<float>(s, q_host, n_levels) : do_init<double>(s, q_host, n_levels);
+}
+
+int at_set_delay_schedule(at_sim* s, int32_t mode, int32_t L, int32_t c_r, uint64_t seed,
+                          const int8_t* table, int64_t n_steps) {
+  if (!s) return fail(AT_E_INVAL, "NULL handle");
+  if (n_steps < 1 || n_steps > (int64_t)1 << 24) return fail(AT_E_INVAL, "n_steps out of range");
+  const int nt = s->g.ntiles;
+  std::vector<int8_t> t((size_t)n_steps * nt * 6, 0);
+  switch (mode) {
+    case AT_SYNC:
+      break;
+    case AT_CAA:
+      if (c_r < 1 || L != c_r - 1) return fail(AT_E_INVAL, "CAA needs c_r >= 1 and L = c_r - 1");
+      for (int64_t n = c_r; n < n_steps; ++n)
+        std::memset(&t[(size_t)n * nt * 6], (int)(n % c_r), (size_t)nt * 6);
+      break;
+    case AT_SAA:
+      if (L < 0) return fail(AT_E_INVAL, "SAA needs L >= 0");
+      for (int64_t n = L + 3; n < n_steps; ++n)
+        for (int ti = 0; ti < nt; ++ti)
+          for (int f = 0; f < 6; ++f) {
+            const uint64_t ctr = ((uint64_t)n * nt + ti) * 6u + f;
+            const uint64_t z = splitmix64(seed, ctr);
+            t[((size_t)n * nt + ti) * 6 + f] = (int8_t)(((z >> 32) * (uint64_t)(L + 1)) >> 32);
+          }
+      break;
+    case AT_EXPLICIT:
+      if (!table) return fail(AT_E_INVAL, "EXPLICIT needs a table");
+      std::memcpy(t.data(), table, t.size());
+      break;
+    default:
+      return fail(AT_E_INVAL, "unknown delay mode");
+  }
+  for (int64_t n = 0; n < n_steps; ++n)
+    for (int i = 0; i < nt * 6; ++i) {
+      const int k = t[(size_t)n * nt * 6 + i];
+      if (k < 0 || k > s->cfg.max_delay || (k > 0 && n - k - 2 < 0))
+        return fail(AT_E_SCHEDULE, "schedule entry out of range or reads a level before 0");
+    }
+  if (s->d_sched) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipFree(s->d_sched));
+    s->d_sched = nullptr;
+  }
+  HIP_TRY(hipMalloc(&s->d_sched, t.size()));
+  HIP_TRY(hipMemcpyAsync(s->d_sched, t.data(), t.size(), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->sched_steps = n_steps;
+  return AT_OK;
+}
+
+int at_set_forcing(at_sim* s, const double* fhat, int64_t n_steps) {
+  if (!s || !fhat) return fail(AT_E_INVAL, "NULL argument");
+  if (!s->cfg.forcing) return fail(AT_E_INVAL, "forcing is disabled in the config");
+  if (n_steps < 1) return fail(AT_E_INVAL, "n_steps < 1");
+  const size_t bytes = sizeof(double) * (size_t)n_steps * kNForce * 6;
+  if (s->d_fhat) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipFree(s->d_fhat));
+    s->d_fhat = nullptr;
+  }
+  HIP_TRY(hipMalloc(&s->d_fhat, bytes));
+  HIP_TRY(hipMemcpyAsync(s->d_fhat, fhat, bytes, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->force_steps = n_steps;
+  return AT_OK;
+}
+
+int at_rhs(at_sim* s, void* out) {
+  if (!s || !out) return fail(AT_E_INVAL, "NULL argument");
+  if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
+  int rc = check_step_tables(s, s->step, 1);
+  if (rc) return rc;
+  return s->cfg.precision == AT_FP32 ? do_rhs<float>(s, out) : do_rhs<double>(s, out);
+}
+
+int at_rk_step(at_sim* s, int32_t n_steps) {
+  if (!s) return fail(AT_E_INVAL, "NULL handle");
+  if (n_steps < 0) return fail(AT_E_INVAL, "n_steps < 0");
+  if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
+  int rc = check_step_tables(s, s->step, n_steps);
+  if (rc) return rc;
+  return s->cfg.precision == AT_FP32 ? do_steps<float>(s, n_steps) : do_steps<double>(s, n_steps);
+}
+
+int at_stats(at_sim* s, at_stats_t* out) {
+  if (!s || !out) return fail(AT_E_INVAL, "NULL argument");
+  if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
+  double st[kNStat + kNQ];
+  int rc = s->cfg.precision == AT_FP32 ? do_stats<float>(s, st) : do_stats<double>(s, st);
+  if (rc) return rc;
+  const double N = (double)s->g.npts;
+  const double vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
+  std::memset(out, 0, sizeof(*out));
+  out->step = s->step;
+  out->time = (double)s->step * s->cfg.dt;
+  out->mass = st[0] * vol;
+  for (int a = 0; a < 3; ++a) out->mom[a] = st[1 + a] * vol;
+  out->energy = st[4] * vol;
+  out->mass_rk = s->tot_init[0] + st[kNStat + 0];
+  for (int a = 0; a < 3; ++a) out->mom_rk[a] = s->tot_init[1 + a] + st[kNStat + 1 + a];
+  out->energy_rk = s->tot_init[4] + st[kNStat + 4];
+  out->K = st[5] / N;
+  out->eps = st[6] / N;
+  out->enstrophy = st[7] / N;
+  out->Mt = std::sqrt(st[8] / N) / std::sqrt(s->cfg.gamma * s->cfg.gas_r * (st[9] / N));
+  out->umax = st[10];
+  out->nonfinite = st[11] != 0.0;
+  return AT_OK;
+}
+
+int at_get_field(at_sim* s, double* q_host) {
+  if (!s || !q_host) return fail(AT_E_INVAL, "NULL argument");
+  if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
+  return s->cfg.precision == AT_FP32 ? do_get_field<float>(s, q_host) : do_get_field<double>(s, q_host);
+}
+
+int at_field_device(at_sim* s, void** ptr) {
+  if (!s || !ptr) return fail(AT_E_INVAL, "NULL argument");
+  if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
+  *ptr = s->ws + s->L.q;
+  return AT_OK;
+}
+
+int at_set_kernel_timing(at_sim* s, int32_t enable) {
+  if (!s) return fail(AT_E_INVAL, "NULL handle");
+  if (enable && !s->timer) {
+    s->timer = new (std::nothrow) EventTimer();
+    if (!s->timer) return fail(AT_E_INVAL, "out of host memory");
+  } else if (!enable && s->timer) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    delete s->timer;
+    s->timer = nullptr;
+  } else if (enable && s->timer) {
+    HIP_TRY(s->timer->harvest(s->stream));
+    s->timer->reset();
+  }
+  return AT_OK;
+}
+
+int at_kernel_timing(at_sim* s, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!s || !total_ms || !launches || kernel < 0 || kernel >= kKCount) return fail(AT_E_INVAL, "bad argument");
+  if (!s->timer) {
+    *total_ms = 0.0;
+    *launches = 0;
+    return AT_OK;
+  }
+  HIP_TRY(s->timer->harvest(s->stream));
+  if (s->timer->failed) return fail(AT_E_HIP, "event creation or record failed");
+  *total_ms = s->timer->total_ms[kernel];
+  *launches = s->timer->launches[kernel];
+  return AT_OK;
+}
+
+const char* at_kernel_name(int32_t kernel) { return kernel_name(kernel); }
+
+int at_destroy(at_sim* s) {
+  if (!s) return AT_OK;
+  (void)hipStreamSynchronize(s->stream);
+  delete s->timer;
+  if (s->d_sched) (void)hipFree(s->d_sched);
+  if (s->d_zero) (void)hipFree(s->d_zero);
+  if (s->d_fhat) (void)hipFree(s->d_fhat);
+  if (s->d_wv) (void)hipFree(s->d_wv);
+  if (s->d_staging) (void)hipFree(s->d_staging);
+  delete s;
+  return AT_OK;
+}
+
+}  // extern "C"

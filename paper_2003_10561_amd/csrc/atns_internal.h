@@ -1,0 +1,106 @@
+// Internal declarations shared by the host side of the C ABI and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "atns.h"
+
+namespace atns {
+
+constexpr int kNQ = 5;        // conserved variables
+constexpr int kNPub = 4;      // published primitives per ghost point: u, v, w, T
+constexpr int kNRing = 9;     // ring components per slab point: u, v, w, T, F_d(0..4)
+constexpr int kNGrad = 12;    // du_i/dx_j (9, index 3 i + j) and dT/dx_j (3, index 9 + j)
+constexpr int kNForce = 40;   // forcing wavevectors
+constexpr int kMaxPairs = 16; // distinct (ky, kz) pairs among them (11 in practice)
+constexpr int kNStat = 13;    // per-block statistic partials
+constexpr int kMaxDelay = 8;
+
+// Grid, virtual-PE tiling and ring geometry (shared by every kernel of one run).
+struct Geom {
+  int n[3];           // points per direction
+  int p[3];           // virtual PEs per direction
+  int e[3];           // PE edge n[d] / p[d]
+  int64_t npts;
+  int64_t slab[3];    // points of one direction's slab set: 4 p_d n_a n_b
+  int64_t ring_dir_off[3];  // element offset of direction d inside one ring slot
+  int64_t ring_slot;  // elements per ring slot = 9 * sum_d slab[d]
+  int R;              // ring slots = max_delay + 3
+  int ntiles;
+};
+
+// Physical constants in the working precision.
+template <typename T>
+struct Coef {
+  T inv12h[3];      // 1 / (12 h_d)
+  T gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
+};
+
+// Forcing: per-step table A[pair][x][c] = sum_kx fhat(kx, pair, c) e^{i kx x} (complex), and the
+// y / z phase tables e^{i ky y} (ky = -2..2) and e^{i kz z} (kz = 0..2).
+template <typename T>
+struct ForceArgs {
+  const T* table;     // [npair][nx][3][2], or null when unforced
+  const T* phase_y;   // [5][ny][2]
+  const T* phase_z;   // [3][nz][2]
+  int npair;
+  int pair_ky[kMaxPairs];
+  int pair_kz[kMaxPairs];
+};
+
+// Work of one RK stage (or one RHS evaluation).
+template <typename T>
+struct StageArgs {
+  Geom g;
+  Coef<T> cf;
+  T* q;               // conserved state [5][N]
+  T* dq;              // RK register [5][N]
+  T* grad;            // [12][N]
+  T* flux;            // [3][5][N]
+  T* ring;            // ring base
+  T* rhs_out;         // RHS-only mode output [5][N] (null in stepping mode)
+  const int8_t* delays;  // [ntiles][6] for this step
+  int64_t step;       // absolute step index n
+  T cstage;           // c_s of this stage
+  T rk_a, rk_b, dt;
+  int publish;        // stage 1: write level n into the ring
+  double* tot_part;   // [nblk][5] FP64 running sums of B_s * sum(dQ) * h^3
+  double vol;         // h_x h_y h_z
+  ForceArgs<T> force;
+};
+
+// Kernel identities for timing (names in kernel_name()).
+enum KernelId { kKGrad = 0, kKFlux = 1, kKUpdate = 2, kKForce = 3, kKStats = 4, kKHistory = 5, kKCount = 6 };
+const char* kernel_name(int id);
+
+// Optional event bracketing of each launch (host side implements it).
+struct LaunchHook {
+  virtual void before(int kernel_id, hipStream_t s) = 0;
+  virtual void after(int kernel_id, hipStream_t s) = 0;
+  virtual ~LaunchHook() = default;
+};
+
+// Launchers (kernels.hip).  All enqueue on `stream`; `hook` may be null.
+template <typename T>
+hipError_t launch_stage(const StageArgs<T>& a, hipStream_t stream, LaunchHook* hook);
+template <typename T>
+hipError_t launch_publish_history(const StageArgs<T>& a, hipStream_t stream);
+template <typename T>
+hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t stream);
+template <typename T>
+hipError_t launch_to_double(const T* src, double* dst, int64_t n, hipStream_t stream);
+template <typename T>
+hipError_t launch_stats(const Geom& g, const Coef<T>& cf, const T* q, double* part, double* out,
+                        const double* tot_part, int64_t ntot_blocks, double gamma, hipStream_t stream,
+                        LaunchHook* hook);
+template <typename T>
+hipError_t launch_force_table(const Geom& g, const double* fhat_step, const int* wv_kx,
+                              const int* wv_pair, int npair, T* table, const T* phase_x,
+                              hipStream_t stream, LaunchHook* hook);
+int64_t update_blocks(const Geom& g);
+int64_t stats_blocks(const Geom& g);
+
+}  // namespace atns

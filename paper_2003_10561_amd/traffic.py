@@ -1,0 +1,32 @@
+"""Algorithmic HBM bytes of one AT RK3 step (what the method must move per grid point).
+
+Per point and step the low-storage RK3 reads and writes the state and its register:
+stage 1 reads Q and writes Q and dQ (15 words), stage 2 reads Q and dQ and writes both (20),
+stage 3 reads Q and dQ and writes Q (15) -> 50 words.  Each step publishes the two face layers
+of every PE (u, v, w, T and the 5 face-normal fluxes: 9 words on a fraction
+phi = 4 (1/ex + 1/ey + 1/ez) of the points), and each stage whose face is delayed reads 3 levels
+of those 9 words on the delayed faces' ghost layers: 27 phi p_d per stage, with p_d the fraction
+of (step, face) pairs whose delay is >= 1.  Halo re-reads of neighbouring points are assumed to be
+served by on-chip caches and are not algorithmic.
+"""
+from __future__ import annotations
+
+
+def ghost_fraction(n, p) -> float:
+    return sum(4.0 * p[d] / n[d] for d in range(3))
+
+
+def words_per_point_step(n, p, p_delayed: float) -> float:
+    phi = ghost_fraction(n, p)
+    return 50.0 + 9.0 * phi + 3.0 * 27.0 * phi * p_delayed
+
+
+def bytes_per_point_step(n, p, p_delayed: float, word: int) -> float:
+    return word * words_per_point_step(n, p, p_delayed)
+
+
+def delayed_fraction(table) -> float:
+    """Fraction of (step, PE, face) entries with delay >= 1 in an int8 schedule table."""
+    import numpy as np
+    t = np.asarray(table)
+    return float((t > 0).mean()) if t.size else 0.0

@@ -18,8 +18,10 @@ schemes"):
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft as sfft
 
 GAMMA = 1.4
 GAS_R = 1.0
@@ -45,47 +47,86 @@ def forcing_wavevectors() -> np.ndarray:
     return np.array(ks, dtype=np.int64)
 
 
-def _wavenumbers(n: int) -> np.ndarray:
-    return np.fft.fftfreq(n, d=1.0 / n)
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
 
 
-def make_velocity(n: int, seed: int, urms2: float, k0: float = 4.0) -> np.ndarray:
+def make_velocity(n: int, seed: int, urms2: float, k0: float = 4.0, log=None) -> np.ndarray:
     """Seeded solenoidal velocity [3][n][n][n] (index order [comp][z][y][x]) on [0, 2pi)^3.
 
-    Fourier modes 0 < |k| < n/2 get complex Gaussian amplitudes, are projected onto the plane
-    normal to k, made Hermitian, scaled per integer shell round(|k|) to the shell energy
-    E(k) ~ k^4 exp(-2 (k/k0)^2), and the whole field is rescaled so that <|u|^2> = urms2.
+    Half-spectrum modes (kx >= 0) with 0 < |k| < n/2 get complex Gaussian amplitudes and are
+    projected onto the plane normal to k; the inverse real FFT gives a real field (Hermitian
+    symmetry is implied).  Its true spectrum is then scaled per integer shell round(|k|) to the
+    shell energy E(k) ~ k^4 exp(-2 (k/k0)^2), and the field is rescaled to <|u|^2> = urms2.
     """
     rng = np.random.default_rng(seed)
-    kk = _wavenumbers(n)
-    kz, ky, kx = np.meshgrid(kk, kk, kk, indexing="ij")
-    kvec = np.stack([kx, ky, kz])  # [3][z][y][x]
-    k2 = kx * kx + ky * ky + kz * kz
+    kf = np.fft.fftfreq(n, d=1.0 / n)
+    kr = np.arange(n // 2 + 1, dtype=np.float64)
+    kz = kf[:, None, None]
+    ky = kf[None, :, None]
+    kx = kr[None, None, :]
+    shp = (n, n, n // 2 + 1)
+    k2 = np.empty(shp)
+    np.add(kx * kx, ky * ky, out=k2)
+    k2 += kz * kz
     kmag = np.sqrt(k2)
     active = (k2 > 0) & (kmag < n / 2)
-    uh = rng.standard_normal((3, n, n, n)) + 1j * rng.standard_normal((3, n, n, n))
-    uh *= active
-    # solenoidal projection (I - k k^T / |k|^2)
-    k2s = np.where(k2 > 0, k2, 1.0)
-    kdotu = (kvec * uh).sum(axis=0)
-    uh = uh - kvec * (kdotu / k2s)
-    # Hermitian part: uh(k) <- (uh(k) + conj(uh(-k))) / 2, so the inverse FFT is real
-    neg = (-np.arange(n)) % n
-    uh_m = uh[:, neg][:, :, neg][:, :, :, neg]
-    uh = 0.5 * (uh + np.conj(uh_m))
-    # shell scaling to the target spectrum
+    uh = np.empty((3,) + shp, dtype=np.complex128)
+    for c in range(3):
+        uh[c].real = rng.standard_normal(shp)
+        uh[c].imag = rng.standard_normal(shp)
+        uh[c] *= active
+    # solenoidal projection (I - k k^T / |k|^2), in place
+    k2[k2 == 0] = 1.0
+    kd = np.empty(shp, dtype=np.complex128)
+    tmp = np.empty(shp, dtype=np.complex128)
+    np.multiply(uh[0], kx, out=kd)
+    np.multiply(uh[1], ky, out=tmp)
+    kd += tmp
+    np.multiply(uh[2], kz, out=tmp)
+    kd += tmp
+    kd /= k2
+    for c, kc in enumerate((kx, ky, kz)):
+        np.multiply(kd, kc, out=tmp)
+        uh[c] -= tmp
+    del kd, tmp
+    if log:
+        log(f"field {n}^3: random projected modes ready")
+    u = sfft.irfftn(uh, s=(n, n, n), axes=(1, 2, 3), workers=_workers())
+    if log:
+        log(f"field {n}^3: first inverse FFT done")
+    # true (Hermitian) spectrum of the real field, then per-shell scaling
+    uh = sfft.rfftn(u, axes=(1, 2, 3), workers=_workers())
+    del u
     shell = np.rint(kmag).astype(np.int64)
-    e_mode = 0.5 * (np.abs(uh) ** 2).sum(axis=0)
+    del kmag
+    e_mode = np.zeros(shp)
+    for c in range(3):
+        e_mode += uh[c].real ** 2
+        e_mode += uh[c].imag ** 2
+    e_mode *= 0.5
+    e_mode[..., 1:(n + 1) // 2] *= 2.0  # modes kx and -kx are both represented by kx > 0
+    e_mode *= active
     nshell = int(shell.max()) + 1
-    e_shell = np.bincount(shell.ravel(), weights=(e_mode * active).ravel(), minlength=nshell)
+    e_shell = np.bincount(shell.ravel(), weights=e_mode.ravel(), minlength=nshell)
+    del e_mode
     ks = np.arange(nshell, dtype=np.float64)
     target = ks ** 4 * np.exp(-2.0 * (ks / k0) ** 2)
-    fac = np.where(e_shell > 0, np.sqrt(np.divide(target, e_shell, out=np.zeros_like(target),
-                                                  where=e_shell > 0)), 0.0)
-    uh = uh * fac[shell]
-    u = np.fft.ifftn(uh, axes=(1, 2, 3)).real
+    fac = np.zeros(nshell)
+    np.divide(target, e_shell, out=fac, where=e_shell > 0)
+    fac = np.sqrt(fac)
+    scale = fac[shell]
+    scale *= active
+    del shell
+    for c in range(3):
+        uh[c] *= scale
+    del scale
+    if log:
+        log(f"field {n}^3: shells scaled")
+    u = sfft.irfftn(uh, s=(n, n, n), axes=(1, 2, 3), workers=_workers())
+    del uh
     u -= u.mean(axis=(1, 2, 3), keepdims=True)
-    cur = float((u * u).sum(axis=0).mean())
+    cur = float(np.einsum("cijk,cijk->", u, u)) / (n ** 3)
     u *= math.sqrt(urms2 / cur)
     return u
 
@@ -95,7 +136,7 @@ def sound_speed(t0: float = 1.0, gamma: float = GAMMA, gas_r: float = GAS_R) -> 
 
 
 def make_field(n: int, seed: int, mt: float = 0.3, k0: float = 4.0, rho0: float = 1.0,
-               t0: float = 1.0, gamma: float = GAMMA, gas_r: float = GAS_R) -> np.ndarray:
+               t0: float = 1.0, gamma: float = GAMMA, gas_r: float = GAS_R, log=None) -> np.ndarray:
     """Initial conservative state Q = (rho, rho u, rho v, rho w, E) as float64 [5][n][n][n].
 
     Uniform density and temperature, velocity from `make_velocity` with
@@ -103,12 +144,17 @@ def make_field(n: int, seed: int, mt: float = 0.3, k0: float = 4.0, rho0: float 
     with c_v = R / (gamma - 1).
     """
     c0 = sound_speed(t0, gamma, gas_r)
-    u = make_velocity(n, seed, (mt * c0) ** 2, k0)
+    u = make_velocity(n, seed, (mt * c0) ** 2, k0, log=log)
     cv = gas_r / (gamma - 1.0)
     q = np.empty((5, n, n, n), dtype=np.float64)
     q[0] = rho0
-    q[1:4] = rho0 * u
-    q[4] = rho0 * (cv * t0 + 0.5 * (u * u).sum(axis=0))
+    np.multiply(u, rho0, out=q[1:4])
+    e = q[4]
+    np.multiply(u[0], u[0], out=e)
+    for c in (1, 2):
+        e += u[c] * u[c]
+    e *= 0.5 * rho0
+    e += rho0 * cv * t0
     return q
 
 

@@ -1,7 +1,10 @@
 import os
 import sys
 
-import pytest
+# large numpy temporaries: skip the transparent-huge-page advice (slow first touch on some hosts)
+os.environ.setdefault("NUMPY_MADVISE_HUGEPAGE", "0")
+
+import pytest  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:

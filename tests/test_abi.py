@@ -1,0 +1,85 @@
+"""C-ABI checks that need no GPU: every symbol of include/atns.h is exported, and argument
+validation happens before any device call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2003_10561_amd import atns
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "atns.h")).read()
+    return sorted(set(re.findall(r"ATNS_API\s+[\w\s\*]+?\b(at_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(atns.LIB_PATH):
+        pytest.skip("libatns.so not built")
+    return atns.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = header_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(atns.EXPORTED) <= set(syms)
+
+
+def test_only_abi_symbols_are_exported(lib):
+    out = os.popen(f"nm -D --defined-only {atns.LIB_PATH}").read().split("\n")
+    ours = [l.split()[-1] for l in out if " T " in l]
+    assert ours and all(s.startswith("at_") for s in ours), ours
+
+
+def cfg(**kw):
+    base = dict(n=(32, 32, 32), p=(2, 2, 1), dt=0.01, mu_ref=0.01, max_delay=3)
+    base.update(kw)
+    return atns.Config(**base)
+
+
+def test_workspace_bytes_formula(lib):
+    c = cfg()
+    b64 = atns.workspace_bytes(c)
+    b32 = atns.workspace_bytes(cfg(precision="fp32"))
+    assert b64 > 0 and b32 > 0 and b32 < b64
+    N = 32 ** 3
+    # state, RK register, 12 gradients, 15 fluxes and the ring: lower bound in FP64
+    phi = 4 * (1 / 16 + 1 / 16 + 1 / 32)
+    ring = 6 * 9 * phi * N
+    assert b64 >= 8 * (5 + 5 + 12 + 15) * N + 8 * ring
+
+
+@pytest.mark.parametrize("bad", [dict(n=(30, 32, 32), p=(4, 2, 1)), dict(p=(16, 2, 1)), dict(order=6),
+                                 dict(max_delay=9), dict(dt=0.0), dict(mu_ref=-1.0),
+                                 dict(gamma=1.0), dict(precision="fp16x")])
+def test_invalid_config_rejected_without_gpu(lib, bad):
+    c = cfg(**bad)
+    cc = c.to_c()
+    if bad.get("precision") == "fp16x":
+        cc.precision = 7
+    assert lib.at_workspace_bytes(C.byref(cc)) == 0
+    h = C.c_void_p()
+    rc = lib.at_create(C.byref(cc), C.c_void_p(256), 1 << 30, None, C.byref(h))
+    assert rc == atns.AT_E_INVAL
+    assert lib.at_last_error().decode() != ""
+
+
+def test_workspace_checks_without_gpu(lib):
+    cc = cfg().to_c()
+    need = lib.at_workspace_bytes(C.byref(cc))
+    h = C.c_void_p()
+    assert lib.at_create(C.byref(cc), None, need, None, C.byref(h)) == atns.AT_E_WORKSPACE
+    assert lib.at_create(C.byref(cc), C.c_void_p(257), need, None, C.byref(h)) == atns.AT_E_WORKSPACE
+    assert lib.at_create(C.byref(cc), C.c_void_p(256), need - 1, None, C.byref(h)) == atns.AT_E_WORKSPACE
+
+
+def test_null_handle_calls(lib):
+    assert lib.at_rk_step(None, 1) == atns.AT_E_INVAL
+    assert lib.at_destroy(None) == atns.AT_OK
+    assert lib.at_version().decode().startswith("atns")
