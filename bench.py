@@ -46,13 +46,18 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
+    ap.add_argument("--zchunk", type=int, default=None)
     return ap.parse_args()
 
 
-def build_sim(atns, W, n, pe, precision, n_steps_total, q, dt, mu, fh):
+def build_sim(atns, W, n, pe, precision, n_steps_total, q, dt, mu, fh, tile=None, zchunk=None):
     cfg = atns.Config(n=(n, n, n), p=(pe, pe, pe), dt=dt, mu_ref=mu, max_delay=3,
                       precision=precision, forcing=True)
     sim = atns.Sim(cfg)
+    if tile is not None or zchunk is not None:
+        t0, z0 = sim.get_tuning()
+        sim.set_tuning(t0 if tile is None else tile, z0 if zchunk is None else zchunk)
     sim.init_field(q)
     sim.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=n_steps_total)
     sim.set_forcing(fh)
@@ -135,13 +140,13 @@ def main():
         sched[s] = s % 4
     pd = traffic.delayed_fraction(sched[Wm:Wm + K])
 
-    sim = build_sim(atns, W, n, pe, "fp32", total, q, dt, mu, fh)
+    sim = build_sim(atns, W, n, pe, "fp32", total, q, dt, mu, fh, args.tile, args.zchunk)
     log("fp32 simulation initialised; timing")
     ms32, kt32 = time_steps(torch, sim, Wm, K)
     st32 = sim.stats()
     del sim
     torch.cuda.empty_cache()
-    log(f"fp32: {ms32 / K:.3f} ms/step; kernels {kt32}")
+    log(f"fp32: {ms32 / K:.3f} ms/step; tuning {args.tile, args.zchunk}; kernels {kt32}")
     rf = roofline(kt32, n, pe, 4, pd, K)
     value = n ** 3 * K / (ms32 * 1e-3)
     out = {"metric": METRIC, "value": value, "unit": "grid-pt-steps/s", "n_gpus": 1, "steps": K,
@@ -155,7 +160,7 @@ def main():
            "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 4) * value / 1e9,
            "stats_after": {k: st32[k] for k in ("K", "eps", "enstrophy", "Mt", "nonfinite")}}
     if not args.no_fp64:
-        sim = build_sim(atns, W, n, pe, "fp64", total, q, dt, mu, fh)
+        sim = build_sim(atns, W, n, pe, "fp64", total, q, dt, mu, fh, args.tile, args.zchunk)
         log("fp64 simulation initialised; timing")
         ms64, kt64 = time_steps(torch, sim, Wm, K)
         st64 = sim.stats()

@@ -100,9 +100,9 @@ ATNS_API const char* at_version(void);
 /* Message for the calling thread's last failing call ("" if none). */
 ATNS_API const char* at_last_error(void);
 
-/* Bytes of device workspace at_create needs for `cfg` (0 if cfg is invalid).  Holds the
- * conserved state, the RK register, derivative and flux scratch, and the ring of published face
- * layers: (max_delay + 3) levels x 9 components (u, v, w, T and the face-normal flux of the five
+/* Bytes of device workspace at_create needs for `cfg` (0 if cfg is invalid).  Holds two conserved
+ * state buffers (a stage reads one and writes the other), the RK register, and the ring of
+ * published face layers: (max_delay + 3) levels x 9 components (u, v, w, T and the face-normal flux of the five
  * conserved variables) x 4 (1/ex + 1/ey + 1/ez) N^3 points. */
 ATNS_API size_t at_workspace_bytes(const at_config* cfg);
 
@@ -159,6 +159,15 @@ ATNS_API int at_get_field(at_sim* sim, double* q_host);
 /* Device pointer to the current conserved state (config precision, [5][nz][ny][nx]); valid until
  * the next call on the handle.  Errors: AT_E_STATE. */
 ATNS_API int at_field_device(at_sim* sim, void** dev_ptr);
+
+/* Launch shape of the fused stage kernel: `tile` (0 .. AT_N_TILES-1) selects the workgroup column
+ * tile and register budget (0: 64x8, 1: 32x8, 2: 32x8 at higher occupancy, 3: 32x4, 4: 64x4,
+ * 5: 16x8 points in x-y), `zchunk` (>= 4) the number of z planes each workgroup marches through.
+ * Results do not depend on either (every point is computed by the same arithmetic); only speed
+ * does.  Set by the autotuner.  Errors: AT_E_INVAL. */
+#define AT_N_TILES 6
+ATNS_API int at_set_tuning(at_sim* sim, int32_t tile, int32_t zchunk);
+ATNS_API int at_get_tuning(at_sim* sim, int32_t* tile, int32_t* zchunk);
 
 /* Kernel timing.  While enabled, every kernel the handle launches is bracketed by two HIP events
  * recorded on the handle's stream; at_kernel_timing synchronises the stream and returns, for kernel

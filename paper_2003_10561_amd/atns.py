@@ -22,7 +22,8 @@ N_FORCE = 40
 EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "at_init_field",
             "at_set_delay_schedule", "at_set_forcing", "at_rhs", "at_rk_step", "at_stats",
             "at_get_field", "at_field_device", "at_destroy", "at_set_kernel_timing",
-            "at_kernel_timing", "at_kernel_name"]
+            "at_kernel_timing", "at_kernel_name", "at_set_tuning", "at_get_tuning"]
+N_TILES = 6
 N_KERNELS = 6
 
 
@@ -78,6 +79,8 @@ def load_library(path: str = LIB_PATH):
     lib.at_kernel_timing.argtypes = [vp, i32, dp, C.POINTER(C.c_int64)]
     lib.at_kernel_name.argtypes = [i32]
     lib.at_kernel_name.restype = C.c_char_p
+    lib.at_set_tuning.argtypes = [vp, i32, i32]
+    lib.at_get_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     _lib = lib
     return lib
 
@@ -212,6 +215,14 @@ class Sim:
         out = np.empty((5,) + self.cfg.shape, dtype=np.float64)
         _check("at_get_field", self.lib.at_get_field(self.h, _dp(out)))
         return out
+
+    def set_tuning(self, tile: int, zchunk: int):
+        _check("at_set_tuning", self.lib.at_set_tuning(self.h, int(tile), int(zchunk)))
+
+    def get_tuning(self):
+        t, z = C.c_int32(), C.c_int32()
+        _check("at_get_tuning", self.lib.at_get_tuning(self.h, C.byref(t), C.byref(z)))
+        return int(t.value), int(z.value)
 
     def set_kernel_timing(self, enable: bool):
         _check("at_set_kernel_timing", self.lib.at_set_kernel_timing(self.h, int(bool(enable))))

@@ -36,8 +36,8 @@ constexpr double kRkC[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t q, dq, grad, flux, ring, tot_part, stat_part, stat_out, force_table, phase_x, phase_y,
-      phase_z, total;
+  size_t q[2], dq, ring, gv, tot_part, stat_part, stat_out, force_table, phase_x, phase_y, phase_z, total;
+  int64_t ntot;  // FP64 total-accumulator slots (an upper bound on fused-stage workgroups)
 };
 
 int validate(const at_config* c) {
@@ -52,6 +52,14 @@ int validate(const at_config* c) {
   if (c->max_delay < 0 || c->max_delay > kMaxDelay) return fail(AT_E_INVAL, "max_delay out of 0..8");
   if (c->precision != AT_FP64 && c->precision != AT_FP32) return fail(AT_E_INVAL, "bad precision");
   if (c->forcing != 0 && c->forcing != 1) return fail(AT_E_INVAL, "forcing must be 0 or 1");
+  {
+    // the stage kernel indexes fields and the ring with 32-bit element offsets
+    const double npts = (double)c->n[0] * c->n[1] * c->n[2];
+    double slab = 0.0;
+    for (int d = 0; d < 3; ++d) slab += 4.0 * c->p[d] * npts / c->n[d];
+    if (kNQ * npts >= 4294967296.0 || (c->max_delay + 3) * kNRing * slab >= 4294967296.0)
+      return fail(AT_E_INVAL, "grid too large for one handle (element offsets must stay below 2^32)");
+  }
   if (!(c->gamma > 1.0) || !(c->gas_r > 0.0) || !(c->prandtl > 0.0) || !(c->t_ref > 0.0) ||
       !(c->mu_ref >= 0.0) || !(c->dt > 0.0) || !std::isfinite(c->mu_exp))
     return fail(AT_E_INVAL, "bad physical parameter");
@@ -89,12 +97,14 @@ Layout make_layout(const at_config* c, const Geom& g) {
     off = align_up(off + bytes);
     return o;
   };
-  L.q = take(kNQ * N * w);
+  L.q[0] = take(kNQ * N * w);
+  L.q[1] = take(kNQ * N * w);
   L.dq = take(kNQ * N * w);
-  L.grad = take(kNGrad * N * w);
-  L.flux = take(3 * kNQ * N * w);
   L.ring = take((size_t)g.R * g.ring_slot * w);
-  L.tot_part = take((size_t)update_blocks(g) * kNQ * 8);
+  L.gv = take((size_t)g.ring_slot * w);
+  // smallest tile (16 x 4) and smallest z chunk (4) bound the workgroup count of any stage launch
+  L.ntot = (int64_t)((c->n[0] + 15) / 16) * ((c->n[1] + 3) / 4) * ((c->n[2] + 3) / 4);
+  L.tot_part = take((size_t)L.ntot * kNQ * 8);
   L.stat_part = take((size_t)stats_blocks(g) * kNStat * 8);
   L.stat_out = take(32 * 8);
   L.force_table = take((size_t)kMaxPairs * c->n[0] * 6 * w);
@@ -180,15 +190,19 @@ struct at_sim {
   uint8_t* ws;
   int8_t* d_sched = nullptr;
   int64_t sched_steps = 0;
+  std::vector<uint8_t> step_delayed;  // per step: does any face read a delayed level
   int8_t* d_zero = nullptr;
   double* d_fhat = nullptr;
   int64_t force_steps = 0;
-  int* d_wv = nullptr;  // [2][40]: kx, pair id
+  int* d_wv = nullptr;  // [2][40] kx and pair id of each wavevector, then [16][2] ky, kz per pair
   int npair = 0;
   int pair_ky[kMaxPairs], pair_kz[kMaxPairs];
   double* d_staging = nullptr;  // 5 N doubles
   int64_t step = 0;
   int initialised = 0;
+  int qcur = 0;                 // which state buffer holds the current state
+  int tile = 1;                 // fused-stage launch shape (index into tile_shape)
+  int zchunk = 64;              // fused-stage z chunk
   double tot_init[kNQ];
   EventTimer* timer = nullptr;  // non-null while kernel timing is enabled
 };
@@ -215,11 +229,12 @@ StageArgs<T> base_args(at_sim* s) {
   StageArgs<T> a{};
   a.g = s->g;
   a.cf = make_coef<T>(s);
-  a.q = (T*)(s->ws + s->L.q);
+  a.q = (T*)(s->ws + s->L.q[s->qcur]);
+  a.q_out = (T*)(s->ws + s->L.q[1 - s->qcur]);
   a.dq = (T*)(s->ws + s->L.dq);
-  a.grad = (T*)(s->ws + s->L.grad);
-  a.flux = (T*)(s->ws + s->L.flux);
   a.ring = (T*)(s->ws + s->L.ring);
+  a.gv_out = (T*)(s->ws + s->L.gv);
+  a.gv = a.gv_out;
   a.tot_part = (double*)(s->ws + s->L.tot_part);
   a.vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
   a.dt = (T)s->cfg.dt;
@@ -227,10 +242,7 @@ StageArgs<T> base_args(at_sim* s) {
   a.force.phase_y = (const T*)(s->ws + s->L.phase_y);
   a.force.phase_z = (const T*)(s->ws + s->L.phase_z);
   a.force.npair = s->npair;
-  for (int i = 0; i < kMaxPairs; ++i) {
-    a.force.pair_ky[i] = s->pair_ky[i];
-    a.force.pair_kz[i] = s->pair_kz[i];
-  }
+  a.force.pair_kyz = s->d_wv + 2 * kNForce;
   return a;
 }
 
@@ -287,12 +299,29 @@ uint64_t splitmix64(uint64_t seed, uint64_t counter) {
 }
 
 template <typename T>
+hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode) {
+  const int id = mode == kModeStepH ? kKStage : (mode == kModeRhsH ? kKRhs : kKPublish);
+  if (s->timer) s->timer->before(id, s->stream);
+  hipError_t e = launch_fused<T>(a, s->tile, s->zchunk, mode, s->stream);
+  if (s->timer) s->timer->after(id, s->stream);
+  return e;
+}
+
+template <typename T>
+hipError_t launch_views(at_sim* s, const StageArgs<T>& a) {
+  if (s->timer) s->timer->before(kKGhost, s->stream);
+  hipError_t e = launch_ghost_views<T>(a, s->stream);
+  if (s->timer) s->timer->after(kKGhost, s->stream);
+  return e;
+}
+
+template <typename T>
 int do_stats(at_sim* s, double* host_out) {
   const Coef<T> cf = make_coef<T>(s);
   double* part = (double*)(s->ws + s->L.stat_part);
   double* out = (double*)(s->ws + s->L.stat_out);
-  HIP_TRY(launch_stats<T>(s->g, cf, (const T*)(s->ws + s->L.q), part, out,
-                          (const double*)(s->ws + s->L.tot_part), update_blocks(s->g), s->cfg.gamma,
+  HIP_TRY(launch_stats<T>(s->g, cf, (const T*)(s->ws + s->L.q[s->qcur]), part, out,
+                          (const double*)(s->ws + s->L.tot_part), s->L.ntot, s->cfg.gamma,
                           s->stream, s->timer));
   HIP_TRY(hipMemcpyAsync(host_out, out, (kNStat + kNQ) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -302,22 +331,25 @@ int do_stats(at_sim* s, double* host_out) {
 template <typename T>
 int do_init(at_sim* s, const double* q_host, int nlev) {
   const int64_t N = s->g.npts;
-  T* q = (T*)(s->ws + s->L.q);
+  s->qcur = 0;
+  T* q = (T*)(s->ws + s->L.q[0]);
   for (int lev = 0; lev < nlev; ++lev) {
     HIP_TRY(hipMemcpyAsync(s->d_staging, q_host + (size_t)lev * kNQ * N, sizeof(double) * kNQ * N,
                            hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_convert<T>(s->d_staging, q, kNQ * N, s->stream));
     if (lev < nlev - 1) {
+      // publish the history level with synchronous derivatives (all delays zero)
       StageArgs<T> a = base_args<T>(s);
       a.delays = s->d_zero;
       a.step = lev;
+      a.step_mod_r = (int)(lev % s->g.R);
       a.cstage = T(0);
       a.publish = 1;
-      HIP_TRY(launch_publish_history<T>(a, s->stream));
+      HIP_TRY(launch_hooked<T>(s, a, kModePublishH));
     }
   }
   HIP_TRY(hipMemsetAsync(s->ws + s->L.dq, 0, sizeof(T) * kNQ * N, s->stream));
-  HIP_TRY(hipMemsetAsync(s->ws + s->L.tot_part, 0, sizeof(double) * kNQ * update_blocks(s->g), s->stream));
+  HIP_TRY(hipMemsetAsync(s->ws + s->L.tot_part, 0, sizeof(double) * kNQ * s->L.ntot, s->stream));
   double st[kNStat + kNQ];
   int rc = do_stats<T>(s, st);
   if (rc) return rc;
@@ -343,6 +375,7 @@ int do_steps(at_sim* s, int nsteps) {
     StageArgs<T> a = base_args<T>(s);
     a.delays = s->d_sched + (size_t)s->step * row;
     a.step = s->step;
+    a.step_mod_r = (int)(s->step % s->g.R);
     if (s->cfg.forcing) {
       T* tab = (T*)(s->ws + s->L.force_table);
       HIP_TRY(launch_force_table<T>(s->g, s->d_fhat + (size_t)s->step * kNForce * 6, s->d_wv,
@@ -351,11 +384,16 @@ int do_steps(at_sim* s, int nsteps) {
       a.force.table = tab;
     }
     for (int st = 0; st < 3; ++st) {
+      a.q = (T*)(s->ws + s->L.q[s->qcur]);
+      a.q_out = (T*)(s->ws + s->L.q[1 - s->qcur]);
       a.cstage = (T)kRkC[st];
       a.rk_a = (T)kRkA[st];
       a.rk_b = (T)kRkB[st];
       a.publish = st == 0;
-      HIP_TRY(launch_stage<T>(a, s->stream, s->timer));
+      a.store_dq = st < 2;
+      if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
+      HIP_TRY(launch_hooked<T>(s, a, kModeStepH));
+      s->qcur = 1 - s->qcur;
     }
     s->step++;
   }
@@ -367,6 +405,7 @@ int do_rhs(at_sim* s, void* out) {
   StageArgs<T> a = base_args<T>(s);
   a.delays = s->d_sched + (size_t)s->step * s->g.ntiles * 6;
   a.step = s->step;
+  a.step_mod_r = (int)(s->step % s->g.R);
   a.cstage = T(0);
   a.rk_a = T(0);
   a.rk_b = T(0);
@@ -379,14 +418,15 @@ int do_rhs(at_sim* s, void* out) {
                                   s->stream, s->timer));
     a.force.table = tab;
   }
-  HIP_TRY(launch_stage<T>(a, s->stream, s->timer));
+  if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
+  HIP_TRY(launch_hooked<T>(s, a, kModeRhsH));
   return AT_OK;
 }
 
 template <typename T>
 int do_get_field(at_sim* s, double* q_host) {
   const int64_t N = s->g.npts;
-  HIP_TRY(launch_to_double<T>((const T*)(s->ws + s->L.q), s->d_staging, kNQ * N, s->stream));
+  HIP_TRY(launch_to_double<T>((const T*)(s->ws + s->L.q[s->qcur]), s->d_staging, kNQ * N, s->stream));
   HIP_TRY(hipMemcpyAsync(q_host, s->d_staging, sizeof(double) * kNQ * N, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return AT_OK;
@@ -421,17 +461,25 @@ int at_create(const at_config* cfg, void* ws, size_t ws_bytes, void* stream, at_
   s->L = L;
   s->stream = (hipStream_t)stream;
   s->ws = (uint8_t*)ws;
+  // default launch shape: 32 x 8 columns if it fits the LDS at this precision, else 16 x 8
+  s->tile = fused_lds_bytes(1, cfg->precision == AT_FP32 ? 4 : 8, cfg->forcing != 0) <= kLdsBytes ? 1 : 5;
+  s->zchunk = cfg->n[2] / cfg->p[2] >= 16 ? cfg->n[2] / cfg->p[2] : cfg->n[2];
+  if (s->zchunk > 128) s->zchunk = 128;
   hipError_t e = hipGetDevice(&s->device);
   if (e == hipSuccess) e = hipMalloc(&s->d_zero, (size_t)g.ntiles * 6);
   if (e == hipSuccess) e = hipMemsetAsync(s->d_zero, 0, (size_t)g.ntiles * 6, s->stream);
   if (e == hipSuccess) e = hipMalloc(&s->d_staging, sizeof(double) * kNQ * g.npts);
-  if (e == hipSuccess) e = hipMalloc(&s->d_wv, sizeof(int) * 2 * kNForce);
+  if (e == hipSuccess) e = hipMalloc(&s->d_wv, sizeof(int) * (2 * kNForce + 2 * kMaxPairs));
   if (e != hipSuccess) {
     at_destroy(s);
     return fail(AT_E_HIP, std::string("allocation: ") + hipGetErrorString(e));
   }
-  int wv[2 * kNForce];
+  int wv[2 * kNForce + 2 * kMaxPairs] = {};
   forcing_lists(wv, wv + kNForce, s->pair_ky, s->pair_kz, &s->npair);
+  for (int i = 0; i < s->npair; ++i) {
+    wv[2 * kNForce + 2 * i] = s->pair_ky[i];
+    wv[2 * kNForce + 2 * i + 1] = s->pair_kz[i];
+  }
   e = hipMemcpyAsync(s->d_wv, wv, sizeof(wv), hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
@@ -495,6 +543,10 @@ int at_set_delay_schedule(at_sim* s, int32_t mode, int32_t L, int32_t c_r, uint6
     HIP_TRY(hipFree(s->d_sched));
     s->d_sched = nullptr;
   }
+  s->step_delayed.assign((size_t)n_steps, 0);
+  for (int64_t n = 0; n < n_steps; ++n)
+    for (int i = 0; i < nt * 6; ++i)
+      if (t[(size_t)n * nt * 6 + i] > 0) s->step_delayed[(size_t)n] = 1;
   HIP_TRY(hipMalloc(&s->d_sched, t.size()));
   HIP_TRY(hipMemcpyAsync(s->d_sched, t.data(), t.size(), hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -571,7 +623,26 @@ int at_get_field(at_sim* s, double* q_host) {
 int at_field_device(at_sim* s, void** ptr) {
   if (!s || !ptr) return fail(AT_E_INVAL, "NULL argument");
   if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
-  *ptr = s->ws + s->L.q;
+  *ptr = s->ws + s->L.q[s->qcur];
+  return AT_OK;
+}
+
+int at_set_tuning(at_sim* s, int32_t tile, int32_t zchunk) {
+  if (!s) return fail(AT_E_INVAL, "NULL handle");
+  if (tile < 0 || tile >= kTileCount) return fail(AT_E_INVAL, "unknown tile shape");
+  if (zchunk < 4) return fail(AT_E_INVAL, "z chunk must be >= 4");
+  const size_t word = s->cfg.precision == AT_FP32 ? 4 : 8;
+  if (fused_lds_bytes(tile, word, s->cfg.forcing != 0) > kLdsBytes)
+    return fail(AT_E_INVAL, "tile shape needs more LDS than a compute unit has at this precision");
+  s->tile = tile;
+  s->zchunk = zchunk > s->cfg.n[2] ? s->cfg.n[2] : zchunk;
+  return AT_OK;
+}
+
+int at_get_tuning(at_sim* s, int32_t* tile, int32_t* zchunk) {
+  if (!s || !tile || !zchunk) return fail(AT_E_INVAL, "NULL argument");
+  *tile = s->tile;
+  *zchunk = s->zchunk;
   return AT_OK;
 }
 

@@ -46,9 +46,8 @@ struct ForceArgs {
   const T* table;     // [npair][nx][3][2], or null when unforced
   const T* phase_y;   // [5][ny][2]
   const T* phase_z;   // [3][nz][2]
+  const int* pair_kyz; // [npair][2]: ky, kz of each pair (device memory)
   int npair;
-  int pair_ky[kMaxPairs];
-  int pair_kz[kMaxPairs];
 };
 
 // Work of one RK stage (or one RHS evaluation).
@@ -56,24 +55,52 @@ template <typename T>
 struct StageArgs {
   Geom g;
   Coef<T> cf;
-  T* q;               // conserved state [5][N]
+  T* q;               // conserved state [5][N] read by the stage
+  T* q_out;           // conserved state written by the stage (the other buffer)
   T* dq;              // RK register [5][N]
-  T* grad;            // [12][N]
-  T* flux;            // [3][5][N]
   T* ring;            // ring base
+  T* gv_out;          // AT views of the face layers for this stage (written by k_ghost_views)
+  const T* gv;        // the same buffer, read by the stage kernel
   T* rhs_out;         // RHS-only mode output [5][N] (null in stepping mode)
   const int8_t* delays;  // [ntiles][6] for this step
   int64_t step;       // absolute step index n
+  int step_mod_r;     // n mod R: ring slot of level n
   T cstage;           // c_s of this stage
   T rk_a, rk_b, dt;
   int publish;        // stage 1: write level n into the ring
+  int store_dq;       // 0 in the last stage (the register is not read again)
   double* tot_part;   // [nblk][5] FP64 running sums of B_s * sum(dQ) * h^3
   double vol;         // h_x h_y h_z
   ForceArgs<T> force;
 };
 
+// Fused-stage launch shapes: BX x BY columns per workgroup and the FP32 occupancy target in
+// waves per SIMD (FP64 uses half).  Chosen per run by the autotuner; results never depend on it.
+struct TileShape {
+  int bx, by, waves;
+};
+constexpr int kTileCount = 6;
+__host__ __device__ constexpr TileShape tile_shape(int t) {
+  return t == 0 ? TileShape{64, 8, 4}
+       : t == 1 ? TileShape{32, 8, 2}
+       : t == 2 ? TileShape{32, 8, 4}
+       : t == 3 ? TileShape{32, 4, 2}
+       : t == 4 ? TileShape{64, 4, 3}
+                : TileShape{16, 8, 2};
+}
+__host__ __device__ inline int tile_bx(int t) { return tile_shape(t).bx; }
+__host__ __device__ inline int tile_by(int t) { return tile_shape(t).by; }
+int64_t fused_blocks(const Geom& g, int tile, int zchunk);
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per compute unit on gfx950
+size_t fused_lds_bytes(int tile, size_t word, bool forced);
+template <typename T>
+hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, hipStream_t stream);
+template <typename T>
+hipError_t launch_ghost_views(const StageArgs<T>& a, hipStream_t stream);
+constexpr int kModeStepH = 0, kModeRhsH = 1, kModePublishH = 2;
+
 // Kernel identities for timing (names in kernel_name()).
-enum KernelId { kKGrad = 0, kKFlux = 1, kKUpdate = 2, kKForce = 3, kKStats = 4, kKHistory = 5, kKCount = 6 };
+enum KernelId { kKStage = 0, kKRhs = 1, kKPublish = 2, kKForce = 3, kKStats = 4, kKGhost = 5, kKCount = 6 };
 const char* kernel_name(int id);
 
 // Optional event bracketing of each launch (host side implements it).
@@ -84,10 +111,6 @@ struct LaunchHook {
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream`; `hook` may be null.
-template <typename T>
-hipError_t launch_stage(const StageArgs<T>& a, hipStream_t stream, LaunchHook* hook);
-template <typename T>
-hipError_t launch_publish_history(const StageArgs<T>& a, hipStream_t stream);
 template <typename T>
 hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t stream);
 template <typename T>
