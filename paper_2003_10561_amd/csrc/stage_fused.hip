@@ -160,9 +160,9 @@ template <typename T, int BX, int BY, int MINW>
 __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, int mode) {
   using TL = Tile<BX, BY>;
   constexpr int LW = TL::LW, LH = TL::LH;
-  __shared__ T s_pr[4][LH][LW];          // u, v, w, T of the current plane
-  __shared__ T s_fx[5][BY][BX + 4];      // F_x on the tile rows, x halo 2
-  __shared__ T s_fy[5][BY + 4][BX];      // F_y on the tile columns, y halo 2
+  __shared__ T s_pr[2][4][LH][LW];       // u, v, w, T of a plane (two buffers: planes alternate)
+  __shared__ T s_fx[2][5][BY][BX + 4];   // F_x on the tile rows, x halo 2
+  __shared__ T s_fy[2][5][BY + 4][BX];   // F_y on the tile columns, y halo 2
   __shared__ double s_tsum[kNQ][TL::NOWN];  // FP64 running sums of dQ per tile column
   // per-column window of the z march (thread-private): u, v, w, T of 5 planes (ring slot
   // z mod 5, index 5 c + slot) and rho, E of 3 planes (index 20 + 3 (c - 4) + z mod 3)
@@ -275,7 +275,7 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
     for (int c = 0; c < kNQ; ++c) acc[j][c] = T(0);
   const int wc = column ? tid : 0;
   if (column) {
-    // planes z0-4 .. z0-1 (z0 itself arrives through `raw` in the first iteration)
+    // planes z0-4 .. z0-1 into the window; z0 arrives through `raw`
 #pragma unroll
     for (int j = 1; j < 5; ++j) {
       const int z = z0 - 5 + j;
@@ -301,15 +301,56 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
 #pragma unroll
     for (int c = 0; c < 5; ++c) xraw[c] = qin[c * N + i1];
   }
+  // window plane z0, then the LDS plane z0 - 2 (buffer parity (z + 2) & 1)
+  if (column) {
+    T r_, u_, v_, w_, t_;
+    prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
+    const int s5 = pmod(z0, 5), s3 = pmod(z0, 3);
+    s_win[0 + s5][wc] = u_;
+    s_win[5 + s5][wc] = v_;
+    s_win[10 + s5][wc] = w_;
+    s_win[15 + s5][wc] = t_;
+    s_win[20 + s3][wc] = r_;
+    s_win[23 + s3][wc] = raw[4];
+    if (z0 + 1 <= z1 + 3) {
+      const uint32_t i = (uint32_t)pmod(z0 + 1, nz) * plane + col;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
+    }
+    const int sp = pmod(z0 - 2, 5);
+    const int b0 = z0 & 1;
+    s_pr[b0][0][py][px] = s_win[0 + sp][wc];
+    s_pr[b0][1][py][px] = s_win[5 + sp][wc];
+    s_pr[b0][2][py][px] = s_win[10 + sp][wc];
+    s_pr[b0][3][py][px] = s_win[15 + sp][wc];
+  }
+  if (ex_ >= 0) {
+    T xr, xu, xv, xw, xt;
+    prim_of<T>(xraw, inv_cv, xr, xu, xv, xw, xt);
+    const uint32_t i = (uint32_t)pmod(z0 - 1, nz) * plane + xcol;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) xraw[c] = qin[c * N + i];
+    const int b0 = z0 & 1;
+    s_pr[b0][0][epy][epx] = xu;
+    s_pr[b0][1][epy][epx] = xv;
+    s_pr[b0][2][epy][epx] = xw;
+    s_pr[b0][3][epy][epx] = xt;
+  }
+  __syncthreads();
 
   // delays of this column's PE, cached per z-PE: the x / y face delays this column's stencils can
-  // cross (0 away from those faces), and both z-face delays
+  // cross (0 away from those faces), and both z-face delays; the previous plane's x / y delays are
+  // kept for its divergence, which runs one plane behind
   int tz_c = -1, kcx = 0, kcy = 0, kzl = 0, kzh = 0;
 
+  // Iteration zc: fluxes of plane zc (LDS buffers of parity zc), x-y divergence of plane zc - 1,
+  // update of plane zc - 2, then the window and LDS plane for zc + 1; one barrier per plane.
   for (int zc = z0 - 2; zc <= z1 + 1; ++zc) {
+    const int bc = (zc + 2) & 1, bd = bc ^ 1;
     const int gz = pmod(zc, nz);
     const int tz = gz / a.ez;
     const int lze = gz - tz * a.ez;
+    const int kcx_d = kcx, kcy_d = kcy;
     if (column && tz != tz_c) {
       tz_c = tz;
       const int8_t* kf = a.delays + ((tz * a.py + ty) * a.px + tx) * 6;
@@ -320,7 +361,9 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
     }
     const int kcz = lze < 2 ? kzl : (lze >= a.ez - 2 ? kzh : 0);
     const bool zin = zc >= z0 && zc < z1;
-    // plane zc - 2 is finalized at the end of this iteration: fetch its state and register now
+    const bool zin_d = zc - 1 >= z0 && zc - 1 < z1;
+    const int gzd = pmod(zc - 1, nz);
+    // plane zc - 2 is finalized in this iteration: fetch its state and register now
     const int zf = zc - 2;
     const bool fin = valid && zf >= z0 && zf < z1 && mode != kModePublish;
     const uint32_t fi = (uint32_t)pmod(zf, nz) * plane + col;
@@ -339,42 +382,6 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
 #pragma unroll
     for (int j = 0; j < 5; ++j) sl5[j] = sb + j >= 5 ? sb + j - 5 : sb + j;
     const int sr = pmod(zc, 3);
-    if (column) {
-      {
-        T r_, u_, v_, w_, t_;
-        prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
-        const int s3 = pmod(zc + 2, 3);
-        s_win[0 + sl5[4]][wc] = u_;
-        s_win[5 + sl5[4]][wc] = v_;
-        s_win[10 + sl5[4]][wc] = w_;
-        s_win[15 + sl5[4]][wc] = t_;
-        s_win[20 + s3][wc] = r_;
-        s_win[23 + s3][wc] = raw[4];
-      }
-      if (zc <= z1) {
-        const uint32_t i = (uint32_t)pmod(zc + 3, nz) * plane + col;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
-      }
-      s_pr[0][py][px] = s_win[0 + sl5[2]][wc];
-      s_pr[1][py][px] = s_win[5 + sl5[2]][wc];
-      s_pr[2][py][px] = s_win[10 + sl5[2]][wc];
-      s_pr[3][py][px] = s_win[15 + sl5[2]][wc];
-    }
-    if (ex_ >= 0) {
-      T xr, xu, xv, xw, xt;
-      prim_of<T>(xraw, inv_cv, xr, xu, xv, xw, xt);
-      if (zc <= z1) {
-        const uint32_t i = (uint32_t)pmod(zc + 1, nz) * plane + xcol;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) xraw[c] = qin[c * N + i];
-      }
-      s_pr[0][epy][epx] = xu;
-      s_pr[1][epy][epx] = xv;
-      s_pr[2][epy][epx] = xw;
-      s_pr[3][epy][epx] = xt;
-    }
-    __syncthreads();
 
     // fluxes of this column at plane zc: the tile computes all three (F_z also just outside the
     // chunk, for the z divergence), the halo rows F_y and the halo columns F_x
@@ -387,10 +394,10 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
       // central derivatives of u, v, w, T: x and y from the LDS plane, z from the window
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        set_grad(G, c, 0, (s_pr[c][py][px - 2] - T(8) * s_pr[c][py][px - 1] +
-                           T(8) * s_pr[c][py][px + 1] - s_pr[c][py][px + 2]) * a.i12x);
-        set_grad(G, c, 1, (s_pr[c][py - 2][px] - T(8) * s_pr[c][py - 1][px] +
-                           T(8) * s_pr[c][py + 1][px] - s_pr[c][py + 2][px]) * a.i12y);
+        set_grad(G, c, 0, (s_pr[bc][c][py][px - 2] - T(8) * s_pr[bc][c][py][px - 1] +
+                           T(8) * s_pr[bc][c][py][px + 1] - s_pr[bc][c][py][px + 2]) * a.i12x);
+        set_grad(G, c, 1, (s_pr[bc][c][py - 2][px] - T(8) * s_pr[bc][c][py - 1][px] +
+                           T(8) * s_pr[bc][c][py + 1][px] - s_pr[bc][c][py + 2][px]) * a.i12y);
         set_grad(G, c, 2, (WIN(c, 0) - T(8) * WIN(c, 1) + T(8) * WIN(c, 3) - WIN(c, 4)) * a.i12z);
       }
       // a stencil that crosses a face with delay k >= 1 is recomputed with the AT values there
@@ -403,7 +410,7 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
             const int m = mi < 2 ? mi - 2 : mi - 1;
             const int l = lxe + m;
             v[mi] = (l < 0 || l >= a.ex) ? ghost<T>(a, 0, c, slab_off(a, 0, pmod(gx + m, nx), gy, gz), kcx)
-                                          : s_pr[c][py][px + m];
+                                          : s_pr[bc][c][py][px + m];
           }
           set_grad(G, c, 0, (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12x);
         }
@@ -417,7 +424,7 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
             const int m = mi < 2 ? mi - 2 : mi - 1;
             const int l = lye + m;
             v[mi] = (l < 0 || l >= a.ey) ? ghost<T>(a, 1, c, slab_off(a, 1, gx, pmod(gy + m, ny), gz), kcy)
-                                          : s_pr[c][py + m][px];
+                                          : s_pr[bc][c][py + m][px];
           }
           set_grad(G, c, 1, (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12y);
         }
@@ -465,7 +472,7 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
         F[4] = Ep * u - (u * s00 + v * s01 + w * s02) - kt * G[9];
         if (need_fx) {
 #pragma unroll
-          for (int c = 0; c < kNQ; ++c) s_fx[c][py - 4][px - 2] = F[c];
+          for (int c = 0; c < kNQ; ++c) s_fx[bc][c][py - 4][px - 2] = F[c];
         }
         if (pubx) {
           const uint32_t sl = a.slab0;
@@ -487,7 +494,7 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
         F[4] = Ep * v - (u * s01 + v * s11 + w * s12) - kt * G[10];
         if (need_fy) {
 #pragma unroll
-          for (int c = 0; c < kNQ; ++c) s_fy[c][py - 2][px - 4] = F[c];
+          for (int c = 0; c < kNQ; ++c) s_fy[bc][c][py - 2][px - 4] = F[c];
         }
         if (puby) {
           const uint32_t sl = a.slab1;
@@ -545,20 +552,19 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
         }
       }
     }
-    __syncthreads();
 
-    if (valid && zin && mode != kModePublish) {
+    if (valid && zin_d && mode != kModePublish) {
       const int fxx = px - 2, fyy = py - 2;  // this point in s_fx (column) and s_fy (row)
 #pragma unroll
       for (int c = 0; c < kNQ; ++c) {
-        const T dfx = (s_fx[c][py - 4][fxx - 2] - T(8) * s_fx[c][py - 4][fxx - 1] + T(8) * s_fx[c][py - 4][fxx + 1] -
-                       s_fx[c][py - 4][fxx + 2]) * a.i12x;
-        const T dfy = (s_fy[c][fyy - 2][px - 4] - T(8) * s_fy[c][fyy - 1][px - 4] + T(8) * s_fy[c][fyy + 1][px - 4] -
-                       s_fy[c][fyy + 2][px - 4]) * a.i12y;
-        acc[2][c] -= dfx + dfy;
+        const T dfx = (s_fx[bd][c][py - 4][fxx - 2] - T(8) * s_fx[bd][c][py - 4][fxx - 1] + T(8) * s_fx[bd][c][py - 4][fxx + 1] -
+                       s_fx[bd][c][py - 4][fxx + 2]) * a.i12x;
+        const T dfy = (s_fy[bd][c][fyy - 2][px - 4] - T(8) * s_fy[bd][c][fyy - 1][px - 4] + T(8) * s_fy[bd][c][fyy + 1][px - 4] -
+                       s_fy[bd][c][fyy + 2][px - 4]) * a.i12y;
+        acc[1][c] -= dfx + dfy;
       }
       // stencils crossing a delayed face: replace the central value by the AT one
-      if (kcx > 0) {
+      if (kcx_d > 0) {
 #pragma unroll
         for (int c = 0; c < kNQ; ++c) {
           T v[4];
@@ -566,16 +572,16 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
           for (int mi = 0; mi < 4; ++mi) {
             const int m = mi < 2 ? mi - 2 : mi - 1;
             const int l = lxe + m;
-            v[mi] = (l < 0 || l >= a.ex) ? ghost<T>(a, 0, 4 + c, slab_off(a, 0, pmod(gx + m, nx), gy, gz), kcx)
-                                          : s_fx[c][py - 4][fxx + m];
+            v[mi] = (l < 0 || l >= a.ex) ? ghost<T>(a, 0, 4 + c, slab_off(a, 0, pmod(gx + m, nx), gy, gzd), kcx_d)
+                                          : s_fx[bd][c][py - 4][fxx + m];
           }
-          const T cen = (s_fx[c][py - 4][fxx - 2] - T(8) * s_fx[c][py - 4][fxx - 1] + T(8) * s_fx[c][py - 4][fxx + 1] -
-                         s_fx[c][py - 4][fxx + 2]) * a.i12x;
+          const T cen = (s_fx[bd][c][py - 4][fxx - 2] - T(8) * s_fx[bd][c][py - 4][fxx - 1] + T(8) * s_fx[bd][c][py - 4][fxx + 1] -
+                         s_fx[bd][c][py - 4][fxx + 2]) * a.i12x;
           const T at = (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12x;
-          add5(acc[2], c, cen - at);
+          add5(acc[1], c, cen - at);
         }
       }
-      if (kcy > 0) {
+      if (kcy_d > 0) {
 #pragma unroll
         for (int c = 0; c < kNQ; ++c) {
           T v[4];
@@ -583,13 +589,13 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
           for (int mi = 0; mi < 4; ++mi) {
             const int m = mi < 2 ? mi - 2 : mi - 1;
             const int l = lye + m;
-            v[mi] = (l < 0 || l >= a.ey) ? ghost<T>(a, 1, 4 + c, slab_off(a, 1, gx, pmod(gy + m, ny), gz), kcy)
-                                          : s_fy[c][fyy + m][px - 4];
+            v[mi] = (l < 0 || l >= a.ey) ? ghost<T>(a, 1, 4 + c, slab_off(a, 1, gx, pmod(gy + m, ny), gzd), kcy_d)
+                                          : s_fy[bd][c][fyy + m][px - 4];
           }
-          const T cen = (s_fy[c][fyy - 2][px - 4] - T(8) * s_fy[c][fyy - 1][px - 4] + T(8) * s_fy[c][fyy + 1][px - 4] -
-                         s_fy[c][fyy + 2][px - 4]) * a.i12y;
+          const T cen = (s_fy[bd][c][fyy - 2][px - 4] - T(8) * s_fy[bd][c][fyy - 1][px - 4] + T(8) * s_fy[bd][c][fyy + 1][px - 4] -
+                         s_fy[bd][c][fyy + 2][px - 4]) * a.i12y;
           const T at = (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12y;
-          add5(acc[2], c, cen - at);
+          add5(acc[1], c, cen - at);
         }
       }
     }
@@ -636,7 +642,47 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
       for (int c = 0; c < kNQ; ++c) acc[j][c] = acc[j + 1][c];
 #pragma unroll
     for (int c = 0; c < kNQ; ++c) acc[4][c] = T(0);
+
+    // prepare plane zc + 1: window gets plane zc + 3 (replacing zc - 2), LDS plane zc + 1
+    if (zc <= z1) {
+      const int bn = bd;  // parity of zc + 1
+      if (column) {
+        T r_, u_, v_, w_, t_;
+        prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
+        const int s3 = pmod(zc + 3, 3);
+        s_win[0 + sl5[0]][wc] = u_;
+        s_win[5 + sl5[0]][wc] = v_;
+        s_win[10 + sl5[0]][wc] = w_;
+        s_win[15 + sl5[0]][wc] = t_;
+        s_win[20 + s3][wc] = r_;
+        s_win[23 + s3][wc] = raw[4];
+        if (zc + 4 <= z1 + 3) {
+          const uint32_t i = (uint32_t)pmod(zc + 4, nz) * plane + col;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
+        }
+        s_pr[bn][0][py][px] = s_win[0 + sl5[3]][wc];
+        s_pr[bn][1][py][px] = s_win[5 + sl5[3]][wc];
+        s_pr[bn][2][py][px] = s_win[10 + sl5[3]][wc];
+        s_pr[bn][3][py][px] = s_win[15 + sl5[3]][wc];
+      }
+      if (ex_ >= 0) {
+        T xr, xu, xv, xw, xt;
+        prim_of<T>(xraw, inv_cv, xr, xu, xv, xw, xt);
+        if (zc + 2 <= z1 + 1) {
+          const uint32_t i = (uint32_t)pmod(zc + 2, nz) * plane + xcol;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) xraw[c] = qin[c * N + i];
+        }
+        s_pr[bn][0][epy][epx] = xu;
+        s_pr[bn][1][epy][epx] = xv;
+        s_pr[bn][2][epy][epx] = xw;
+        s_pr[bn][3][epy][epx] = xt;
+      }
+    }
+    __syncthreads();
   }
+
 
   if (mode != kModeStep) return;  // uniform across the grid
   // FP64 block sums of B_s * sum(dQ) * h^3 into this workgroup's slot (fixed order)
@@ -709,14 +755,26 @@ FArgs<T> pack(const StageArgs<T>& s, int zchunk) {
   return a;
 }
 
+// Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950).
+template <typename T, int BX, int BY>
+constexpr size_t stage_static_lds() {
+  using TL = Tile<BX, BY>;
+  return sizeof(T) * (2 * (4 * TL::LH * TL::LW + 5 * BY * (BX + 4) + 5 * (BY + 4) * BX) + 26 * TL::NCOL) +
+         8 * kNQ * TL::NOWN;
+}
+
 template <typename T, int BX, int BY, int MINW>
 hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, hipStream_t stream) {
-  const Geom& g = s.g;
-  const dim3 grid((g.n[0] + BX - 1) / BX, (g.n[1] + BY - 1) / BY, (g.n[2] + zchunk - 1) / zchunk);
-  const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
-  hipLaunchKernelGGL((k_stage<T, BX, BY, MINW>), grid, dim3(Tile<BX, BY>::NT), dyn, stream,
-                     pack<T>(s, zchunk), mode);
-  return hipGetLastError();
+  if constexpr (stage_static_lds<T, BX, BY>() > kLdsBytes) {
+    return hipErrorInvalidConfiguration;
+  } else {
+    const Geom& g = s.g;
+    const dim3 grid((g.n[0] + BX - 1) / BX, (g.n[1] + BY - 1) / BY, (g.n[2] + zchunk - 1) / zchunk);
+    const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
+    hipLaunchKernelGGL((k_stage<T, BX, BY, MINW>), grid, dim3(Tile<BX, BY>::NT), dyn, stream,
+                       pack<T>(s, zchunk), mode);
+    return hipGetLastError();
+  }
 }
 
 // AT views of all published face-layer points for one stage: for a point on layer 0/1 (2/3) of
@@ -807,9 +865,7 @@ int64_t fused_blocks(const Geom& g, int tile, int zchunk) {
 // LDS bytes of a stage launch (static arrays plus the forcing coefficients when forced).
 template <int BX, int BY>
 size_t stage_lds_bytes(size_t w, bool forced) {
-  using TL = Tile<BX, BY>;
-  const size_t stat = w * (4 * TL::LH * TL::LW + 5 * BY * (BX + 4) + 5 * (BY + 4) * BX + 26 * TL::NCOL) +
-                      8 * kNQ * TL::NOWN;
+  const size_t stat = w == 4 ? stage_static_lds<float, BX, BY>() : stage_static_lds<double, BX, BY>();
   return stat + (forced ? w * 18 * BX * BY : 0);
 }
 
@@ -829,15 +885,11 @@ hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, h
   if (fused_lds_bytes(tile, sizeof(T), a.force.table != nullptr) > kLdsBytes) return hipErrorInvalidConfiguration;
   constexpr bool f32 = sizeof(T) == 4;
   switch (tile) {
-    case 0:
-      if constexpr (f32) return launch_cfg<T, 64, 8, 4>(a, zchunk, mode, stream);
-      return hipErrorInvalidConfiguration;
+    case 0: return launch_cfg<T, 64, 8, f32 ? 4 : 2>(a, zchunk, mode, stream);
     case 1: return launch_cfg<T, 32, 8, f32 ? 2 : 1>(a, zchunk, mode, stream);
     case 2: return launch_cfg<T, 32, 8, f32 ? 4 : 2>(a, zchunk, mode, stream);
     case 3: return launch_cfg<T, 32, 4, f32 ? 2 : 1>(a, zchunk, mode, stream);
-    case 4:
-      if constexpr (f32) return launch_cfg<T, 64, 4, 3>(a, zchunk, mode, stream);
-      return hipErrorInvalidConfiguration;
+    case 4: return launch_cfg<T, 64, 4, f32 ? 3 : 2>(a, zchunk, mode, stream);
     case 5: return launch_cfg<T, 16, 8, f32 ? 2 : 1>(a, zchunk, mode, stream);
     default: return hipErrorInvalidValue;
   }
