@@ -18,6 +18,7 @@ os.environ.setdefault("NUMPY_MADVISE_HUGEPAGE", "0")
 import argparse  # noqa: E402
 import json  # noqa: E402
 import math  # noqa: E402
+import re  # noqa: E402
 import sys  # noqa: E402
 import time  # noqa: E402
 
@@ -48,6 +49,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
     ap.add_argument("--zchunk", type=int, default=None)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-run workload")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served request trace")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the Poisson arrival window")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON lines)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -81,10 +89,15 @@ def time_steps(torch, sim, warmup, steps):
     return ms, kt
 
 
+STAGE_KERNELS = ("k_stage", "k_ghost_views")
+
+
 def roofline(kt, n, pe, word, pd, steps):
-    """Dominant launch = one RK stage (its kernels); algorithmic bytes per stage launch."""
+    """Dominant launch = one RK stage: the fused stage kernel plus, at delayed stages, the AT face
+    views it reads (the method's delayed-level reads).  Algorithmic bytes per stage launch over
+    the average event-timed duration of those kernels per stage."""
     from paper_2003_10561_amd import traffic
-    stage_kernels = [k for k in kt if k in ("k_grad", "k_flux", "k_update", "k_stage")]
+    stage_kernels = [k for k in kt if k in STAGE_KERNELS]
     launches = steps * 3
     stage_ms = sum(kt[k][0] for k in stage_kernels) / launches
     words = traffic.words_per_point_step((n,) * 3, (pe,) * 3, pd) / 3.0
@@ -95,6 +108,137 @@ def roofline(kt, n, pe, word, pd, steps):
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": stage_ms,
             "algorithmic_bytes_per_point_step": words * 3 * word}
+
+
+def stage_source_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2003_10561_amd", "csrc", "stage_fused.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(n, pe, precision):
+    """HBM bytes per stage launch from the committed counter summary, if it was taken on the
+    current stage-kernel source for this workload; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"k_stage_{n}_pe{pe}_{precision}_traffic.md")
+    # written by paper_2003_10561_amd/profsum.py from FETCH_SIZE / WRITE_SIZE runs of this bench
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^- (\w+): (\S+)\s*$", line)
+            if m:
+                kv[m.group(1)] = m.group(2)
+    if kv.get("source_sha256") != stage_source_sha() or "bytes_per_launch" not in kv:
+        return None
+    return float(kv["bytes_per_launch"])
+
+
+def calib_copy(torch, mib):
+    """A plain device copy of known size: the reference the HBM counters are scaled by."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_each_way": n * 4, "launches": 3}), flush=True)
+
+
+def batch_specs(seed0=1000):
+    """64 runs: 16 each of N = 32, 64, 96, 128 (PE tiles 16^3 at N = 32, else 32^3), M_t ~ U[0.1, 0.5],
+    mu_ref = default(N) x logU[0.5, 2], delays CAA or SAA with equal odds, L ~ U{1, 2, 3}; run i seeded
+    with seed0 + i."""
+    specs = []
+    for i in range(64):
+        rng = np.random.default_rng(seed0 + i)
+        n = (32, 64, 96, 128)[i // 16]
+        specs.append(dict(n=n, p=2 if n == 32 else n // 32, mt=float(rng.uniform(0.1, 0.5)),
+                          mu_scale=float(np.exp(rng.uniform(np.log(0.5), np.log(2.0)))),
+                          mode="caa" if rng.random() < 0.5 else "saa", L=int(rng.integers(1, 4)),
+                          seed=seed0 + i))
+    return specs
+
+
+def batched_workload(torch, atns, W, steps, warmup, cache):
+    specs = batch_specs()
+    sims = []
+    total = warmup + steps + 1
+    for sp in specs:
+        n = sp["n"]
+        q = W.make_field(n, sp["seed"], sp["mt"])
+        cfg = atns.Config(n=(n,) * 3, p=(sp["p"],) * 3, dt=W.default_dt(q), mu_ref=W.default_mu(n) * sp["mu_scale"],
+                          max_delay=sp["L"], precision="fp32")
+        s = atns.Sim(cfg)
+        s.init_field(q)
+        if sp["mode"] == "caa":
+            s.set_delay_schedule(atns.CAA, L=sp["L"], c_r=sp["L"] + 1, n_steps=total)
+        else:
+            s.set_delay_schedule(atns.SAA, L=sp["L"], seed=sp["seed"], n_steps=total)
+        sims.append(s)
+    b = atns.Batch("fp32")
+    for s in sims:
+        b.add(s)
+    tune_ms = b.autotune(cache, reps=3)
+    tile, zc = b.get_tuning()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    b.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    pts = sum(sp["n"] ** 3 for sp in specs)
+    caps, reps = b.graph_stats()
+    nonfinite = sum(s.stats()["nonfinite"] for s in sims)
+    b.close()
+    del sims
+    torch.cuda.empty_cache()
+    return {"value": pts * steps / (ms * 1e-3), "unit": "grid-pt-steps/s", "runs": len(specs), "points": pts,
+            "steps": steps, "warmup": warmup, "ms_per_step": ms / steps, "tile": tile, "zchunk": zc,
+            "autotune_stage_ms": tune_ms, "graph_captures": caps, "graph_replays": reps,
+            "nonfinite_runs": int(nonfinite),
+            "workload": "64 runs (16 each of 32^3, 64^3, 96^3, 128^3), CAA/SAA L in 1..3, FP32, one batched "
+                        "launch per kernel per RK stage from a HIP graph"}
+
+
+def served_workload(atns, W, seconds, seed=5):
+    """Poisson arrivals at 20/s for `seconds`; N = 32 round(exp(U(ln 32, ln 256)) / 32); steps ~ U{20..200};
+    delays as in the batched workload; request j seeded with 5000 + j.  Initial fields come from a pool of
+    two seeded fields per size (building one per request on the host would dominate the latency)."""
+    rng = np.random.default_rng(seed)
+    t, reqs = 0.0, []
+    pool = {}
+    while True:
+        t += float(rng.exponential(1.0 / 20.0))
+        if t > seconds:
+            break
+        j = len(reqs)
+        n = int(32 * round(float(np.exp(rng.uniform(np.log(32), np.log(256)))) / 32))
+        n = max(32, n)
+        key = (n, j % 2)
+        if key not in pool:
+            q = W.make_field(n, 5000 + 10 * n + key[1], 0.3)
+            pool[key] = (q, W.default_dt(q))
+        q, dt = pool[key]
+        mode = atns.CAA if rng.random() < 0.5 else atns.SAA
+        L = int(rng.integers(1, 4))
+        reqs.append(dict(arrival_s=t, n=n, p=2 if n == 32 else n // 32, steps=int(rng.integers(20, 201)),
+                         mode=mode, L=L, seed=5000 + j, dt=dt, mu_ref=W.default_mu(n), q0=q))
+    res, makespan = atns.serve(reqs, precision="fp32", max_active=64, hbm_budget_bytes=200e9)
+    ok = [o for o in res if o["status"] == 0]
+    lat = np.array([o["done_s"] - r["arrival_s"] for r, o in zip(reqs, res) if o["status"] == 0])
+    work = sum(r["n"] ** 3 * r["steps"] for r, o in zip(reqs, res) if o["status"] == 0)
+    offered = sum(r["n"] ** 3 * r["steps"] for r in reqs) / seconds
+    return {"requests": len(reqs), "served": len(ok), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "throughput": work / makespan,
+            "unit": "grid-pt-steps/s", "offered_load": offered, "makespan_s": makespan,
+            "arrival_window_s": seconds, "nonfinite": int(sum(o["stats"]["nonfinite"] for o in ok)),
+            "workload": "Poisson 20/s, N log-uniform 32..256 (multiples of 32), 20..200 steps, CAA/SAA L 1..3, "
+                        "FP32, continuous batching"}
 
 
 def cpu_baseline(W, n, steps):
@@ -125,6 +269,9 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.calib_copy_mib:
+        calib_copy(torch, args.calib_copy_mib)
+        return
     from paper_2003_10561_amd import atns, traffic, workload as W
 
     n, pe, K, Wm = args.n, args.pe, args.steps, args.warmup
@@ -148,6 +295,7 @@ def main():
     torch.cuda.empty_cache()
     log(f"fp32: {ms32 / K:.3f} ms/step; tuning {args.tile, args.zchunk}; kernels {kt32}")
     rf = roofline(kt32, n, pe, 4, pd, K)
+    rf["traffic"] = measured_traffic(n, pe, "fp32")
     value = n ** 3 * K / (ms32 * 1e-3)
     out = {"metric": METRIC, "value": value, "unit": "grid-pt-steps/s", "n_gpus": 1, "steps": K,
            "warmup": Wm, "ms_per_step": ms32 / K, "higher_is_better": True, "scaling": "weak",
@@ -175,6 +323,14 @@ def main():
                        "fp32_speedup": value / v64,
                        "fp32_vs_fp64_stats_rel": {k: abs(st32[k] - st64[k]) / abs(st64[k])
                                                   for k in ("K", "eps", "enstrophy", "Mt")}}
+    if not args.no_batch:
+        log("batched 64-run workload ...")
+        out["batched"] = batched_workload(torch, atns, W, args.batch_steps, 2, args.tune_cache)
+        log(f"batched: {out['batched']}")
+    if not args.no_serve:
+        log("served trace ...")
+        out["served"] = served_workload(atns, W, args.serve_seconds)
+        log(f"served: {out['served']}")
     if not args.no_cpu:
         log("cpu oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_n, args.cpu_steps)

@@ -178,8 +178,101 @@ ATNS_API int at_set_kernel_timing(at_sim* sim, int32_t enable);
 ATNS_API int at_kernel_timing(at_sim* sim, int32_t kernel, double* total_ms, int64_t* launches);
 ATNS_API const char* at_kernel_name(int32_t kernel);
 
-/* Release the handle and the library's own allocations (not the workspace or stream). */
+/* Release the handle and the library's own allocations (not the workspace or stream).  A run that
+ * is a member of a batch leaves it. */
 ATNS_API int at_destroy(at_sim* sim);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched runs.  Many independent runs (any grid, PE grid, delays, forcing, time step and
+ * viscosity; one precision) advanced together: one launch per kernel per RK stage covers the
+ * workgroups of every member, reading each member's arguments from a device run table through a
+ * (run, workgroup) work list; the launches of a call are captured in a HIP graph and the graph is
+ * replayed while membership, launch shape and chunk length stay the same.  Each member's state,
+ * step counter and outputs are bitwise those it would have if stepped alone with at_rk_step at the
+ * batch's launch shape.  Members keep their own handles (at_stats, at_get_field, at_rhs work as
+ * usual between batched steps) and must use the batch's stream and device.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct at_batch at_batch;
+
+/* New empty batch for runs of `precision` (AT_FP32 / AT_FP64) enqueueing on hip_stream (NULL =
+ * default stream).  The library allocates the batch's run tables and pinned staging itself.
+ * Errors: AT_E_INVAL, AT_E_HIP. */
+ATNS_API int at_batch_create(int32_t precision, void* hip_stream, at_batch** out);
+
+/* Add an initialised run (joins at its current step; members may be at different steps).
+ * Errors: AT_E_INVAL (precision, stream or device differ; batch full; a forced run with a tile
+ * shape that does not fit), AT_E_STATE (not initialised, already in a batch). */
+ATNS_API int at_batch_add(at_batch* batch, at_sim* sim);
+
+/* Remove a member (it keeps its state and can be stepped alone).  Errors: AT_E_STATE. */
+ATNS_API int at_batch_remove(at_batch* batch, at_sim* sim);
+ATNS_API int at_batch_size(at_batch* batch, int32_t* n_runs);
+
+/* Enqueue n_steps (0 .. 4096) RK steps of every member, each at its own step counter and with its
+ * own schedule and forcing.  Asynchronous on the batch stream.  Errors: AT_E_SCHEDULE (a member's
+ * tables do not cover its steps), AT_E_INVAL, AT_E_HIP. */
+ATNS_API int at_batch_step(at_batch* batch, int32_t n_steps);
+
+/* Launch shape of the batched stage launches (same meaning as at_set_tuning; never changes a
+ * field value).  Errors: AT_E_INVAL. */
+ATNS_API int at_batch_set_tuning(at_batch* batch, int32_t tile, int32_t zchunk);
+ATNS_API int at_batch_get_tuning(at_batch* batch, int32_t* tile, int32_t* zchunk);
+
+/* Choose the launch shape: looks up the device and the members' shapes in cache_path (JSON
+ * lines; NULL = no cache) and otherwise times `reps` trial stages of every feasible (tile, z chunk)
+ * and appends the fastest to the cache.  A trial rewrites only buffers that are dead between steps
+ * (the second state buffer and the RK register) and discards its conserved totals, so the
+ * members' states are unchanged.  *best_ms (may be NULL) receives the stage time.  Synchronises.
+ * Errors: AT_E_STATE (empty batch), AT_E_SCHEDULE, AT_E_INVAL, AT_E_HIP. */
+ATNS_API int at_batch_autotune(at_batch* batch, const char* cache_path, int32_t reps, double* best_ms);
+
+/* Graph capture on (default) or off (launches enqueued directly); graph capture and replay counts. */
+ATNS_API int at_batch_set_graph(at_batch* batch, int32_t enable);
+ATNS_API int at_batch_graph_stats(at_batch* batch, int64_t* captures, int64_t* replays);
+
+/* Release the batch (members stay valid and leave it). */
+ATNS_API int at_batch_destroy(at_batch* batch);
+
+/* ---------------------------------------------------------------------------------------------
+ * Served runs (continuous batching).  at_serve replays a request trace against the wall clock:
+ * a request becomes visible at its arrival time, is admitted first come first served when fewer
+ * than max_active runs are active and its device footprint (workspace, staging, schedule) fits
+ * both the HBM budget and the free device memory, joins the batch at the next step boundary,
+ * and leaves at the boundary where it has done its steps, after its final statistics (and field,
+ * if asked) are read back.  The server allocates and frees the workspaces itself.  Unforced cubes
+ * only; each request's delays are AT_SYNC, AT_CAA (c_r = L + 1) or AT_SAA (seed).
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t precision;        /* AT_FP32 | AT_FP64 */
+  int32_t max_active;       /* slots: runs served at once */
+  int32_t tile, zchunk;     /* batch launch shape (tile < 0: library default) */
+  double hbm_budget_bytes;  /* device bytes the server may hold for admitted runs */
+} at_serve_config;
+
+typedef struct {
+  double arrival_s;         /* arrival, seconds after the start of serving; non-decreasing */
+  int32_t n, p;             /* n^3 grid, p^3 virtual PEs */
+  int32_t steps;            /* RK steps to run */
+  int32_t mode, L;          /* AT_SYNC | AT_CAA | AT_SAA, delay bound (max_delay = L) */
+  uint64_t seed;            /* AT_SAA seed */
+  double dt, mu_ref;
+  const double* q0;         /* host float64 [5][n][n][n]: initial state (read at admission) */
+  double* q_final;          /* host float64 [5][n][n][n] for the final state, or NULL */
+} at_request;
+
+typedef struct {
+  double admit_s, done_s;   /* seconds after the start: admission, completion (stats read back) */
+  at_stats_t stats;         /* final statistics */
+  int32_t status;           /* AT_OK, or the error that ended this request */
+  int32_t reserved;
+} at_result;
+
+/* Serve nreq requests on hip_stream; blocks until every request has completed or failed.
+ * results[i] belongs to reqs[i]; *makespan_s (may be NULL) receives the serving wall time.
+ * Errors: AT_E_INVAL (bad arguments or an invalid request), AT_E_HIP; a request that can never
+ * fit gets status AT_E_WORKSPACE without failing the call. */
+ATNS_API int at_serve(const at_serve_config* cfg, const at_request* reqs, int32_t nreq, void* hip_stream,
+                      at_result* results, double* makespan_s);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,10 @@ N_FORCE = 40
 EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "at_init_field",
             "at_set_delay_schedule", "at_set_forcing", "at_rhs", "at_rk_step", "at_stats",
             "at_get_field", "at_field_device", "at_destroy", "at_set_kernel_timing",
-            "at_kernel_timing", "at_kernel_name", "at_set_tuning", "at_get_tuning"]
+            "at_kernel_timing", "at_kernel_name", "at_set_tuning", "at_get_tuning",
+            "at_batch_create", "at_batch_add", "at_batch_remove", "at_batch_size", "at_batch_step",
+            "at_batch_set_tuning", "at_batch_get_tuning", "at_batch_autotune", "at_batch_set_graph",
+            "at_batch_graph_stats", "at_batch_destroy", "at_serve"]
 N_TILES = 6
 N_KERNELS = 6
 
@@ -47,6 +50,22 @@ class _Stats(C.Structure):
                 ("mom_rk", C.c_double * 3), ("energy_rk", C.c_double), ("K", C.c_double),
                 ("eps", C.c_double), ("enstrophy", C.c_double), ("Mt", C.c_double),
                 ("umax", C.c_double), ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _ServeConfig(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_active", C.c_int32), ("tile", C.c_int32),
+                ("zchunk", C.c_int32), ("hbm_budget_bytes", C.c_double)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("arrival_s", C.c_double), ("n", C.c_int32), ("p", C.c_int32), ("steps", C.c_int32),
+                ("mode", C.c_int32), ("L", C.c_int32), ("seed", C.c_uint64), ("dt", C.c_double),
+                ("mu_ref", C.c_double), ("q0", C.POINTER(C.c_double)), ("q_final", C.POINTER(C.c_double))]
+
+
+class _Result(C.Structure):
+    _fields_ = [("admit_s", C.c_double), ("done_s", C.c_double), ("stats", _Stats), ("status", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -81,6 +100,18 @@ def load_library(path: str = LIB_PATH):
     lib.at_kernel_name.restype = C.c_char_p
     lib.at_set_tuning.argtypes = [vp, i32, i32]
     lib.at_get_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.at_batch_create.argtypes = [i32, vp, C.POINTER(vp)]
+    lib.at_batch_add.argtypes = [vp, vp]
+    lib.at_batch_remove.argtypes = [vp, vp]
+    lib.at_batch_size.argtypes = [vp, C.POINTER(C.c_int32)]
+    lib.at_batch_step.argtypes = [vp, i32]
+    lib.at_batch_set_tuning.argtypes = [vp, i32, i32]
+    lib.at_batch_get_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.at_batch_autotune.argtypes = [vp, C.c_char_p, i32, dp]
+    lib.at_batch_set_graph.argtypes = [vp, i32]
+    lib.at_batch_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.at_batch_destroy.argtypes = [vp]
+    lib.at_serve.argtypes = [C.POINTER(_ServeConfig), C.POINTER(_Request), i32, vp, C.POINTER(_Result), dp]
     _lib = lib
     return lib
 
@@ -140,6 +171,14 @@ def workspace_bytes(cfg: Config) -> int:
 
 def _dp(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stats_dict(s: _Stats) -> dict:
+    return {"step": s.step, "time": s.time, "mass": s.mass, "momx": s.mom[0], "momy": s.mom[1],
+            "momz": s.mom[2], "energy": s.energy, "mass_rk": s.mass_rk, "momx_rk": s.mom_rk[0],
+            "momy_rk": s.mom_rk[1], "momz_rk": s.mom_rk[2], "energy_rk": s.energy_rk, "K": s.K,
+            "eps": s.eps, "enstrophy": s.enstrophy, "Mt": s.Mt, "umax": s.umax,
+            "nonfinite": s.nonfinite}
 
 
 class Sim:
@@ -205,11 +244,7 @@ class Sim:
     def stats(self) -> dict:
         s = _Stats()
         _check("at_stats", self.lib.at_stats(self.h, C.byref(s)))
-        return {"step": s.step, "time": s.time, "mass": s.mass, "momx": s.mom[0], "momy": s.mom[1],
-                "momz": s.mom[2], "energy": s.energy, "mass_rk": s.mass_rk, "momx_rk": s.mom_rk[0],
-                "momy_rk": s.mom_rk[1], "momz_rk": s.mom_rk[2], "energy_rk": s.energy_rk, "K": s.K,
-                "eps": s.eps, "enstrophy": s.enstrophy, "Mt": s.Mt, "umax": s.umax,
-                "nonfinite": s.nonfinite}
+        return _stats_dict(s)
 
     def get_field(self) -> np.ndarray:
         out = np.empty((5,) + self.cfg.shape, dtype=np.float64)
@@ -241,3 +276,99 @@ class Sim:
         p = C.c_void_p()
         _check("at_field_device", self.lib.at_field_device(self.h, C.byref(p)))
         return int(p.value)
+
+
+class Batch:
+    """Batched runs (include/atns.h, at_batch_*): members advance together, one launch per kernel
+    per RK stage, replayed from a HIP graph.  Members must share the batch's precision and stream."""
+
+    def __init__(self, precision: str = "fp32", stream=None):
+        import torch
+        self.lib = load_library()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check("at_batch_create", self.lib.at_batch_create(FP32 if precision == "fp32" else FP64,
+                                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.members = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.at_batch_destroy(self.h)
+            self.h = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, sim: Sim):
+        _check("at_batch_add", self.lib.at_batch_add(self.h, sim.h))
+        self.members.append(sim)
+
+    def remove(self, sim: Sim):
+        _check("at_batch_remove", self.lib.at_batch_remove(self.h, sim.h))
+        self.members = [m for m in self.members if m is not sim]
+
+    def __len__(self):
+        n = C.c_int32()
+        _check("at_batch_size", self.lib.at_batch_size(self.h, C.byref(n)))
+        return int(n.value)
+
+    def step(self, n_steps: int = 1):
+        _check("at_batch_step", self.lib.at_batch_step(self.h, int(n_steps)))
+
+    def set_tuning(self, tile: int, zchunk: int):
+        _check("at_batch_set_tuning", self.lib.at_batch_set_tuning(self.h, int(tile), int(zchunk)))
+
+    def get_tuning(self):
+        t, z = C.c_int32(), C.c_int32()
+        _check("at_batch_get_tuning", self.lib.at_batch_get_tuning(self.h, C.byref(t), C.byref(z)))
+        return int(t.value), int(z.value)
+
+    def autotune(self, cache_path=None, reps: int = 3) -> float:
+        ms = C.c_double()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check("at_batch_autotune", self.lib.at_batch_autotune(self.h, path, int(reps), C.byref(ms)))
+        return float(ms.value)
+
+    def set_graph(self, enable: bool):
+        _check("at_batch_set_graph", self.lib.at_batch_set_graph(self.h, int(bool(enable))))
+
+    def graph_stats(self):
+        c, r = C.c_int64(), C.c_int64()
+        _check("at_batch_graph_stats", self.lib.at_batch_graph_stats(self.h, C.byref(c), C.byref(r)))
+        return int(c.value), int(r.value)
+
+
+def serve(requests, precision: str = "fp32", max_active: int = 64, hbm_budget_bytes: float = 64e9,
+          tile: int = -1, zchunk: int = 64, stream=None):
+    """Serve a request trace with continuous batching (at_serve).  Each request is a dict with
+    arrival_s, n, p, steps, mode, L, seed, dt, mu_ref, q0 (float64 [5][n][n][n]) and optionally
+    q_final (a float64 array of the same shape that receives the final state).  Returns
+    (list of {admit_s, done_s, status, stats}, makespan in s)."""
+    import torch
+    lib = load_library()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    sc = _ServeConfig(FP32 if precision == "fp32" else FP64, int(max_active), int(tile), int(zchunk),
+                      float(hbm_budget_bytes))
+    n = len(requests)
+    reqs = (_Request * max(n, 1))()
+    keep = []
+    for i, r in enumerate(requests):
+        q0 = np.ascontiguousarray(r["q0"], dtype=np.float64)
+        keep.append(q0)
+        qf = r.get("q_final")
+        if qf is not None:
+            assert qf.dtype == np.float64 and qf.flags.c_contiguous and qf.shape == q0.shape
+        reqs[i] = _Request(float(r["arrival_s"]), int(r["n"]), int(r["p"]), int(r["steps"]), int(r["mode"]),
+                           int(r["L"]), C.c_uint64(int(r.get("seed", 0))), float(r["dt"]), float(r["mu_ref"]),
+                           _dp(q0), _dp(qf) if qf is not None else None)
+    res = (_Result * max(n, 1))()
+    mk = C.c_double()
+    _check("at_serve", lib.at_serve(C.byref(sc), reqs, n, C.c_void_p(st.cuda_stream), res, C.byref(mk)))
+    out = [{"admit_s": res[i].admit_s, "done_s": res[i].done_s, "status": res[i].status,
+            "stats": _stats_dict(res[i].stats)} for i in range(n)]
+    return out, float(mk.value)

@@ -1,5 +1,6 @@
 // Host side of the C ABI (include/atns.h): validation, workspace layout, schedules, forcing
 // tables, and the stage loop of the low-storage RK3 step.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -7,11 +8,11 @@
 #include <string>
 #include <vector>
 
-#include "atns_internal.h"
+#include "sim_internal.h"
 
 using namespace atns;
 
-namespace {
+namespace atns {
 
 thread_local std::string g_last_error;
 
@@ -20,25 +21,19 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                    \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess) return fail(AT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+int check_step_tables(at_sim* s, int64_t first, int64_t count) {
+  if (!s->d_sched || first + count > s->sched_steps)
+    return fail(AT_E_SCHEDULE, "delay schedule does not cover the requested steps");
+  if (s->cfg.forcing && (!s->d_fhat || first + count > s->force_steps))
+    return fail(AT_E_SCHEDULE, "forcing table does not cover the requested steps");
+  return AT_OK;
+}
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
+}  // namespace atns
 
-// Williamson (1980) low-storage RK3 coefficients.
-constexpr double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
-constexpr double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
-constexpr double kRkC[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
+namespace {
 
-size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-struct Layout {
-  size_t q[2], dq, ring, gv, tot_part, stat_part, stat_out, force_table, phase_x, phase_y, phase_z, total;
-  int64_t ntot;  // FP64 total-accumulator slots (an upper bound on fused-stage workgroups)
-};
 
 int validate(const at_config* c) {
   if (!c) return fail(AT_E_INVAL, "config is NULL");
@@ -106,7 +101,7 @@ Layout make_layout(const at_config* c, const Geom& g) {
   L.ntot = (int64_t)((c->n[0] + 15) / 16) * ((c->n[1] + 3) / 4) * ((c->n[2] + 3) / 4);
   L.tot_part = take((size_t)L.ntot * kNQ * 8);
   L.stat_part = take((size_t)stats_blocks(g) * kNStat * 8);
-  L.stat_out = take(32 * 8);
+  L.stat_out = take(kStatOutBytes);
   L.force_table = take((size_t)kMaxPairs * c->n[0] * 6 * w);
   L.phase_x = take((size_t)5 * c->n[0] * 2 * w);
   L.phase_y = take((size_t)5 * c->n[1] * 2 * w);
@@ -115,8 +110,10 @@ Layout make_layout(const at_config* c, const Geom& g) {
   return L;
 }
 
+}  // namespace
+
 // HIP events around each launch; pairs are harvested when timings are queried.
-struct EventTimer final : LaunchHook {
+struct atns::EventTimer final : LaunchHook {
   struct Pending {
     int id;
     hipEvent_t a, b;
@@ -179,72 +176,9 @@ struct EventTimer final : LaunchHook {
   }
 };
 
-}  // namespace
-
-struct at_sim {
-  at_config cfg;
-  Geom g;
-  Layout L;
-  hipStream_t stream;
-  int device;
-  uint8_t* ws;
-  int8_t* d_sched = nullptr;
-  int64_t sched_steps = 0;
-  std::vector<uint8_t> step_delayed;  // per step: does any face read a delayed level
-  int8_t* d_zero = nullptr;
-  double* d_fhat = nullptr;
-  int64_t force_steps = 0;
-  int* d_wv = nullptr;  // [2][40] kx and pair id of each wavevector, then [16][2] ky, kz per pair
-  int npair = 0;
-  int pair_ky[kMaxPairs], pair_kz[kMaxPairs];
-  double* d_staging = nullptr;  // 5 N doubles
-  int64_t step = 0;
-  int initialised = 0;
-  int qcur = 0;                 // which state buffer holds the current state
-  int tile = 1;                 // fused-stage launch shape (index into tile_shape)
-  int zchunk = 64;              // fused-stage z chunk
-  double tot_init[kNQ];
-  EventTimer* timer = nullptr;  // non-null while kernel timing is enabled
-};
-
 namespace {
 
-template <typename T>
-Coef<T> make_coef(const at_sim* s) {
-  Coef<T> cf{};
-  for (int d = 0; d < 3; ++d) cf.inv12h[d] = (T)(1.0 / (12.0 * (kTwoPi / s->cfg.n[d])));
-  const double cv = s->cfg.gas_r / (s->cfg.gamma - 1.0);
-  const double cp = s->cfg.gamma * s->cfg.gas_r / (s->cfg.gamma - 1.0);
-  cf.gas_r = (T)s->cfg.gas_r;
-  cf.inv_cv = (T)(1.0 / cv);
-  cf.cp_over_pr = (T)(cp / s->cfg.prandtl);
-  cf.mu_ref = (T)s->cfg.mu_ref;
-  cf.inv_tref = (T)(1.0 / s->cfg.t_ref);
-  cf.mu_exp = (T)s->cfg.mu_exp;
-  return cf;
-}
 
-template <typename T>
-StageArgs<T> base_args(at_sim* s) {
-  StageArgs<T> a{};
-  a.g = s->g;
-  a.cf = make_coef<T>(s);
-  a.q = (T*)(s->ws + s->L.q[s->qcur]);
-  a.q_out = (T*)(s->ws + s->L.q[1 - s->qcur]);
-  a.dq = (T*)(s->ws + s->L.dq);
-  a.ring = (T*)(s->ws + s->L.ring);
-  a.gv_out = (T*)(s->ws + s->L.gv);
-  a.gv = a.gv_out;
-  a.tot_part = (double*)(s->ws + s->L.tot_part);
-  a.vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
-  a.dt = (T)s->cfg.dt;
-  a.force.table = nullptr;
-  a.force.phase_y = (const T*)(s->ws + s->L.phase_y);
-  a.force.phase_z = (const T*)(s->ws + s->L.phase_z);
-  a.force.npair = s->npair;
-  a.force.pair_kyz = s->d_wv + 2 * kNForce;
-  return a;
-}
 
 // Forcing wavevectors in the documented order, and the (ky, kz) pair of each.
 void forcing_lists(int kx[kNForce], int pair[kNForce], int pky[kMaxPairs], int pkz[kMaxPairs],
@@ -321,7 +255,7 @@ int do_stats(at_sim* s, double* host_out) {
   double* part = (double*)(s->ws + s->L.stat_part);
   double* out = (double*)(s->ws + s->L.stat_out);
   HIP_TRY(launch_stats<T>(s->g, cf, (const T*)(s->ws + s->L.q[s->qcur]), part, out,
-                          (const double*)(s->ws + s->L.tot_part), s->L.ntot, s->cfg.gamma,
+                          (const double*)(s->ws + s->L.tot_part), s->tot_used, s->cfg.gamma,
                           s->stream, s->timer));
   HIP_TRY(hipMemcpyAsync(host_out, out, (kNStat + kNQ) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -350,6 +284,7 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
   }
   HIP_TRY(hipMemsetAsync(s->ws + s->L.dq, 0, sizeof(T) * kNQ * N, s->stream));
   HIP_TRY(hipMemsetAsync(s->ws + s->L.tot_part, 0, sizeof(double) * kNQ * s->L.ntot, s->stream));
+  s->tot_used = 0;
   double st[kNStat + kNQ];
   int rc = do_stats<T>(s, st);
   if (rc) return rc;
@@ -360,17 +295,11 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
   return AT_OK;
 }
 
-int check_step_tables(at_sim* s, int64_t first, int64_t count) {
-  if (!s->d_sched || first + count > s->sched_steps)
-    return fail(AT_E_SCHEDULE, "delay schedule does not cover the requested steps");
-  if (s->cfg.forcing && (!s->d_fhat || first + count > s->force_steps))
-    return fail(AT_E_SCHEDULE, "forcing table does not cover the requested steps");
-  return AT_OK;
-}
 
 template <typename T>
 int do_steps(at_sim* s, int nsteps) {
   const size_t row = (size_t)s->g.ntiles * 6;
+  if (nsteps > 0) s->tot_used = std::max(s->tot_used, fused_blocks(s->g, s->tile, s->zchunk));
   for (int it = 0; it < nsteps; ++it) {
     StageArgs<T> a = base_args<T>(s);
     a.delays = s->d_sched + (size_t)s->step * row;
@@ -566,6 +495,7 @@ int at_set_forcing(at_sim* s, const double* fhat, int64_t n_steps) {
   }
   HIP_TRY(hipMalloc(&s->d_fhat, bytes));
   HIP_TRY(hipMemcpyAsync(s->d_fhat, fhat, bytes, hipMemcpyHostToDevice, s->stream));
+  s->h_fhat.assign(fhat, fhat + (size_t)n_steps * kNForce * 6);
   HIP_TRY(hipStreamSynchronize(s->stream));
   s->force_steps = n_steps;
   return AT_OK;
@@ -681,6 +611,7 @@ const char* at_kernel_name(int32_t kernel) { return kernel_name(kernel); }
 int at_destroy(at_sim* s) {
   if (!s) return AT_OK;
   (void)hipStreamSynchronize(s->stream);
+  if (s->batch) batch_forget(s->batch, s);
   delete s->timer;
   if (s->d_sched) (void)hipFree(s->d_sched);
   if (s->d_zero) (void)hipFree(s->d_zero);

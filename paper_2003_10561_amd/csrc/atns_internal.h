@@ -18,6 +18,11 @@ constexpr int kNForce = 40;   // forcing wavevectors
 constexpr int kMaxPairs = 16; // distinct (ky, kz) pairs among them (11 in practice)
 constexpr int kNStat = 13;    // per-block statistic partials
 constexpr int kMaxDelay = 8;
+// Statistics output region: 18 doubles (13 statistics, 5 RK totals) in the first kStatOutSlots,
+// then the kStatRed level-1 rows of the two-level reduction.
+constexpr int kStatOutSlots = 32;
+constexpr int kStatRed = 256;
+constexpr size_t kStatOutBytes = sizeof(double) * (kStatOutSlots + (size_t)kStatRed * (kNStat + 5));
 
 // Grid, virtual-PE tiling and ring geometry (shared by every kernel of one run).
 struct Geom {
@@ -97,6 +102,19 @@ template <typename T>
 hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, hipStream_t stream);
 template <typename T>
 hipError_t launch_ghost_views(const StageArgs<T>& a, hipStream_t stream);
+
+// Batched launches (one launch over the workgroups of many runs).  A run table is an array of
+// batch_arg_bytes<T>() records written by pack_batch_arg; work lists hold (run, local block).
+template <typename T>
+size_t batch_arg_bytes();
+template <typename T>
+void pack_batch_arg(const StageArgs<T>& s, int tile, int zchunk, int views, void* dst);
+template <typename T>
+hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, int mode,
+                              hipStream_t stream);
+template <typename T>
+hipError_t launch_views_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream);
+int64_t view_blocks(const Geom& g);  // 256-point blocks of k_ghost_views for one run
 constexpr int kModeStepH = 0, kModeRhsH = 1, kModePublishH = 2;
 
 // Kernel identities for timing (names in kernel_name()).

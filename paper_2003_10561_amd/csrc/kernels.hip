@@ -131,30 +131,58 @@ __global__ __launch_bounds__(256) void k_stats(Geom g, Coef<T> cf, const T* __re
 }
 
 // Fixed-order final reduction: out[0..12] statistics, out[13..17] RK totals partial sums.
-__global__ __launch_bounds__(256) void k_stats_final(const double* __restrict__ part, int64_t nblk,
-                                                     const double* __restrict__ tot_part,
-                                                     int64_t ntot, double* __restrict__ out) {
+// Fixed-order two-level reduction of the per-block partials (deterministic: the order depends only
+// on the partial counts).  Level 1: workgroup j reduces its contiguous share of the statistic
+// partials [nblk][13] and of the FP64 RK-total slots [ntot][5] into mid[j][18]; level 2 reduces
+// the kStatRed rows of mid into out[18].  Components 10 (max |u|) and 11 (non-finite flag) take
+// the maximum, the others the sum.
+constexpr int kStatOut = kNStat + kNQ;
+static_assert(kStatRed == 256, "level 2 gives one thread per level-1 row");
+
+__device__ __forceinline__ double tree256(double* red, double v, bool is_max) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] = is_max ? fmax(red[t], red[t + s]) : red[t] + red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_stats_reduce(const double* __restrict__ part, int64_t nblk,
+                                                      const double* __restrict__ tot_part, int64_t ntot,
+                                                      double* __restrict__ mid) {
   __shared__ double red[256];
   const int t = threadIdx.x;
-  for (int c = 0; c < kNStat + kNQ; ++c) {
+  const int64_t j = blockIdx.x;
+  const int64_t lp = (nblk + kStatRed - 1) / kStatRed, lt = (ntot + kStatRed - 1) / kStatRed;
+  const int64_t p0 = j * lp, p1 = min(p0 + lp, nblk), t0 = j * lt, t1 = min(t0 + lt, ntot);
+  for (int c = 0; c < kStatOut; ++c) {
     const bool is_max = (c == 10 || c == 11);
     double v = 0.0;
     if (c < kNStat) {
-      for (int64_t b = t; b < nblk; b += 256) {
+      for (int64_t b = p0 + t; b < p1; b += 256) {
         const double pv = part[b * kNStat + c];
         v = is_max ? fmax(v, pv) : v + pv;
       }
     } else if (tot_part) {
-      for (int64_t b = t; b < ntot; b += 256) v += tot_part[b * kNQ + (c - kNStat)];
+      for (int64_t b = t0 + t; b < t1; b += 256) v += tot_part[b * kNQ + (c - kNStat)];
     }
-    red[t] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) red[t] = is_max ? fmax(red[t], red[t + s]) : red[t] + red[t + s];
-      __syncthreads();
-    }
-    if (t == 0) out[c] = red[0];
-    __syncthreads();
+    const double r = tree256(red, v, is_max);
+    if (t == 0) mid[j * kStatOut + c] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_stats_final(const double* __restrict__ mid, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  for (int c = 0; c < kStatOut; ++c) {
+    const bool is_max = (c == 10 || c == 11);
+    const double r = tree256(red, t < kStatRed ? mid[t * kStatOut + c] : 0.0, is_max);
+    if (t == 0) out[c] = r;
   }
 }
 
@@ -242,8 +270,10 @@ hipError_t launch_stats(const Geom& g, const Coef<T>& cf, const T* q, double* pa
   const dim3 blk(kBX, kBY, 1);
   const dim3 gr = grid_of(g);
   HOOKED(kKStats, hipLaunchKernelGGL(k_stats<T>, gr, blk, 0, stream, g, cf, q, part));
-  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, stream, part, stats_blocks(g), tot_part,
-                     ntot_blocks, out);
+  double* mid = out + kStatOutSlots;
+  hipLaunchKernelGGL(k_stats_reduce, dim3(kStatRed), dim3(256), 0, stream, part, stats_blocks(g), tot_part,
+                     ntot_blocks, mid);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, stream, (const double*)mid, out);
   return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@
 //
 // Indexing is 32-bit (element offsets below 2^32, checked by the host) and every per-column
 // quantity is computed once; per-plane quantities are uniform across the workgroup.
+#include <cstring>
+
 #include "atns_internal.h"
 
 namespace atns {
@@ -46,6 +48,8 @@ struct FArgs {
   uint32_t rdir1, rdir2, rslot;  // ring offsets of directions 1, 2 in a slot; slot size
   int nx, ny, nz, px, py, ex, ey, ez;
   int R, step_mod_r, npair, zchunk, publish, store_dq;
+  int gbx, gby;  // workgroups along x and y (a batched launch decodes its local block with them)
+  int views;     // batched ghost views: does this run read delayed levels at this stage
   T i12x, i12y, i12z, gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
   T cstage, rk_a, rk_b, dt;
   double vol;
@@ -155,9 +159,11 @@ __device__ __forceinline__ void add5(T acc[kNQ], int c, T val) {
 // window element of component c (0 u, 1 v, 2 w, 3 T) at plane index j (plane zc - 2 + j)
 #define WIN(c, j) s_win[5 * (c) + sl5[j]][wc]
 
-// MINW: waves per SIMD the register allocation must allow (occupancy target).
-template <typename T, int BX, int BY, int MINW>
-__global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, int mode) {
+// One workgroup of a stage: the BX x BY column tile (bkx, bky) and z chunk bkz of run `a`; `blk`
+// is its slot among the run's workgroups for the FP64 totals.
+template <typename T, int BX, int BY>
+__device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, const int bkx, const int bky,
+                                           const int bkz, const uint32_t blk) {
   using TL = Tile<BX, BY>;
   constexpr int LW = TL::LW, LH = TL::LH;
   __shared__ T s_pr[2][4][LH][LW];       // u, v, w, T of a plane (two buffers: planes alternate)
@@ -173,7 +179,7 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const uint32_t N = a.N, plane = a.plane;
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY, z0 = blockIdx.z * a.zchunk;
+  const int x0 = bkx * BX, y0 = bky * BY, z0 = bkz * a.zchunk;
   const int xe = min(x0 + BX, nx), ye = min(y0 + BY, ny), z1 = min(z0 + a.zchunk, nz);
 
   // role and column of this thread
@@ -694,10 +700,40 @@ __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, 
     }
     __syncthreads();
   }
-  if (tid < kNQ) {
-    const uint32_t blk = ((uint32_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    a.tot_part[blk * kNQ + tid] += (double)a.rk_b * s_tsum[tid][0] * a.vol;
-  }
+  if (tid < kNQ) a.tot_part[blk * kNQ + tid] += (double)a.rk_b * s_tsum[tid][0] * a.vol;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (dispatch index w goes to XCD w mod 8), and
+// each XCD has its own L2.  Logical workgroup L = xcd_major(w, nb) gives XCD c the contiguous range
+// of logical workgroups [c q + min(c, r), ...) (q = nb / 8, r = nb mod 8, XCDs below r take one
+// more), so workgroups that share halo planes run on the same L2.  A bijection of [0, nb).
+constexpr uint32_t kNumXcd = 8;
+__device__ __forceinline__ uint32_t xcd_major(uint32_t w, uint32_t nb) {
+  const uint32_t c = w % kNumXcd, i = w / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
+  return c * q + min(c, r) + i;
+}
+
+// MINW: waves per SIMD the register allocation must allow (occupancy target).
+template <typename T, int BX, int BY, int MINW>
+__global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, int mode) {
+  const uint32_t gx = (uint32_t)a.gbx, gxy = gx * (uint32_t)a.gby;
+  const uint32_t L = xcd_major(blockIdx.x, gridDim.x);
+  const uint32_t bz = L / gxy, r = L - bz * gxy, by = r / gx, bx = r - by * gx;
+  stage_body<T, BX, BY>(a, mode, (int)bx, (int)by, (int)bz, L);
+}
+
+// Batched stage: one launch over the workgroups of many runs.  work[b] = (run, local workgroup);
+// the run's arguments come from the device run table, so each run sees exactly the workgroup
+// decomposition (and therefore the arithmetic) of its own single-run launch.
+template <typename T, int BX, int BY, int MINW>
+__global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage_batch(const FArgs<T>* __restrict__ runs,
+                                                                          const uint2* __restrict__ work,
+                                                                          int mode) {
+  const uint2 w = work[xcd_major(blockIdx.x, gridDim.x)];
+  const FArgs<T> a = runs[w.x];
+  const uint32_t per = (uint32_t)a.gbx * (uint32_t)a.gby;
+  const uint32_t bz = w.y / per, r = w.y - bz * per, by = r / (uint32_t)a.gbx, bx = r - by * (uint32_t)a.gbx;
+  stage_body<T, BX, BY>(a, mode, (int)bx, (int)by, (int)bz, w.y);
 }
 
 template <typename T>
@@ -736,6 +772,9 @@ FArgs<T> pack(const StageArgs<T>& s, int zchunk) {
   a.step_mod_r = s.step_mod_r;
   a.npair = s.force.npair;
   a.zchunk = zchunk;
+  a.gbx = (g.n[0] + 15) / 16;  // set to the launch tile's workgroup counts by the launchers
+  a.gby = (g.n[1] + 3) / 4;
+  a.views = 0;
   a.publish = s.publish;
   a.store_dq = s.store_dq;
   a.i12x = s.cf.inv12h[0];
@@ -769,10 +808,15 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, hipStream_t s
     return hipErrorInvalidConfiguration;
   } else {
     const Geom& g = s.g;
-    const dim3 grid((g.n[0] + BX - 1) / BX, (g.n[1] + BY - 1) / BY, (g.n[2] + zchunk - 1) / zchunk);
+    // a 1-D grid (the kernel decodes its logical x / y / z workgroup), with gridDim.y and gridDim.z
+    // carried as 1 so that the decode below sees (gx, gy, gz) = (grid x, grid y, grid z)
+    const unsigned gx = (unsigned)((g.n[0] + BX - 1) / BX), gy = (unsigned)((g.n[1] + BY - 1) / BY),
+                   gz = (unsigned)((g.n[2] + zchunk - 1) / zchunk);
+    FArgs<T> a = pack<T>(s, zchunk);
+    a.gbx = (int)gx;
+    a.gby = (int)gy;
     const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
-    hipLaunchKernelGGL((k_stage<T, BX, BY, MINW>), grid, dim3(Tile<BX, BY>::NT), dyn, stream,
-                       pack<T>(s, zchunk), mode);
+    hipLaunchKernelGGL((k_stage<T, BX, BY, MINW>), dim3(gx * gy * gz), dim3(Tile<BX, BY>::NT), dyn, stream, a, mode);
     return hipGetLastError();
   }
 }
@@ -782,8 +826,7 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, hipStream_t s
 // the view is w_0 v^{n-k} + w_1 v^{n-k-1} + w_2 v^{n-k-2}, w from kappa = k + c_s (Sec. 2.1,
 // Eq. at; Appendix B weights at c_s = 0).  Points whose reader has k = 0 are not written.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ghost_views(FArgs<T> a, T* __restrict__ gv) {
-  const uint32_t tid = blockIdx.x * 256u + threadIdx.x;
+__device__ __forceinline__ void ghost_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid) {
   const uint32_t total = a.slab0 + a.slab1 + a.slab2;
   if (tid >= total) return;
   int d, x, y, z, jp;
@@ -844,6 +887,22 @@ __global__ __launch_bounds__(256) void k_ghost_views(FArgs<T> a, T* __restrict__
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_ghost_views(FArgs<T> a, T* __restrict__ gv) {
+  ghost_body<T>(a, gv, blockIdx.x * 256u + threadIdx.x);
+}
+
+// Batched views: work[b] = (run, local block of 256 face-layer points); runs that read no
+// delayed level at this stage leave at once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ghost_views_batch(const FArgs<T>* __restrict__ runs,
+                                                           const uint2* __restrict__ work) {
+  const uint2 w = work[blockIdx.x];
+  const FArgs<T> a = runs[w.x];
+  if (!a.views) return;
+  ghost_body<T>(a, const_cast<T*>(a.gv), w.y * 256u + threadIdx.x);
+}
+
 }  // namespace
 
 template <typename T>
@@ -897,5 +956,70 @@ hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, h
 
 template hipError_t launch_fused<double>(const StageArgs<double>&, int, int, int, hipStream_t);
 template hipError_t launch_fused<float>(const StageArgs<float>&, int, int, int, hipStream_t);
+
+template <typename T>
+size_t batch_arg_bytes() {
+  return sizeof(FArgs<T>);
+}
+
+template <typename T>
+void pack_batch_arg(const StageArgs<T>& s, int tile, int zchunk, int views, void* dst) {
+  FArgs<T> a = pack<T>(s, zchunk);
+  a.gbx = (s.g.n[0] + tile_bx(tile) - 1) / tile_bx(tile);
+  a.gby = (s.g.n[1] + tile_by(tile) - 1) / tile_by(tile);
+  a.views = views;
+  std::memcpy(dst, &a, sizeof(a));
+}
+
+int64_t view_blocks(const Geom& g) { return (g.slab[0] + g.slab[1] + g.slab[2] + 255) / 256; }
+
+namespace {
+template <typename T, int BX, int BY, int MINW>
+hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, bool forced, int mode,
+                            hipStream_t stream) {
+  if constexpr (stage_static_lds<T, BX, BY>() > kLdsBytes) {
+    return hipErrorInvalidConfiguration;
+  } else {
+    const size_t dyn = forced ? sizeof(T) * 18 * BX * BY : 0;
+    hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW>), dim3((unsigned)nblk), dim3(Tile<BX, BY>::NT), dyn,
+                       stream, (const FArgs<T>*)runs, work, mode);
+    return hipGetLastError();
+  }
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, int mode,
+                              hipStream_t stream) {
+  if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidValue;
+  if (fused_lds_bytes(tile, sizeof(T), forced) > kLdsBytes) return hipErrorInvalidConfiguration;
+  constexpr bool f32 = sizeof(T) == 4;
+  switch (tile) {
+    case 0: return launch_batch_cfg<T, 64, 8, f32 ? 4 : 2>(runs, work, nblk, forced, mode, stream);
+    case 1: return launch_batch_cfg<T, 32, 8, f32 ? 2 : 1>(runs, work, nblk, forced, mode, stream);
+    case 2: return launch_batch_cfg<T, 32, 8, f32 ? 4 : 2>(runs, work, nblk, forced, mode, stream);
+    case 3: return launch_batch_cfg<T, 32, 4, f32 ? 2 : 1>(runs, work, nblk, forced, mode, stream);
+    case 4: return launch_batch_cfg<T, 64, 4, f32 ? 3 : 2>(runs, work, nblk, forced, mode, stream);
+    case 5: return launch_batch_cfg<T, 16, 8, f32 ? 2 : 1>(runs, work, nblk, forced, mode, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_views_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream) {
+  if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ghost_views_batch<T>, dim3((unsigned)nblk), dim3(256), 0, stream, (const FArgs<T>*)runs,
+                     work);
+  return hipGetLastError();
+}
+
+template size_t batch_arg_bytes<float>();
+template size_t batch_arg_bytes<double>();
+template void pack_batch_arg<float>(const StageArgs<float>&, int, int, int, void*);
+template void pack_batch_arg<double>(const StageArgs<double>&, int, int, int, void*);
+template hipError_t launch_fused_batch<float>(const void*, const uint2*, int64_t, int, bool, int, hipStream_t);
+template hipError_t launch_fused_batch<double>(const void*, const uint2*, int64_t, int, bool, int, hipStream_t);
+template hipError_t launch_views_batch<float>(const void*, const uint2*, int64_t, hipStream_t);
+template hipError_t launch_views_batch<double>(const void*, const uint2*, int64_t, hipStream_t);
 
 }  // namespace atns

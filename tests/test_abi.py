@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2003_10561_amd import atns
@@ -86,3 +87,28 @@ def test_null_handle_calls(lib):
     assert lib.at_rk_step(None, 1) == atns.AT_E_INVAL
     assert lib.at_destroy(None) == atns.AT_OK
     assert lib.at_version().decode().startswith("atns")
+
+
+def test_batch_and_serve_argument_checks_without_gpu(lib):
+    """Argument errors are reported before any device call."""
+    assert lib.at_batch_step(None, 1) == atns.AT_E_INVAL
+    assert lib.at_batch_add(None, None) == atns.AT_E_INVAL
+    assert lib.at_batch_autotune(None, None, 3, None) == atns.AT_E_INVAL
+    assert lib.at_batch_destroy(None) == atns.AT_OK
+    h = C.c_void_p()
+    assert lib.at_batch_create(7, None, C.byref(h)) == atns.AT_E_INVAL
+    sc = atns._ServeConfig(atns.FP32, 4, -1, 64, 1e9)
+    assert lib.at_serve(None, None, 0, None, None, None) == atns.AT_E_INVAL
+    q = np.zeros((5, 16, 16, 16))
+    reqs = (atns._Request * 2)()
+    for i, t in enumerate((0.5, 0.1)):  # arrivals out of order
+        reqs[i] = atns._Request(t, 16, 2, 3, atns.SYNC, 0, 0, 0.01, 0.01,
+                                q.ctypes.data_as(C.POINTER(C.c_double)), None)
+    res = (atns._Result * 2)()
+    assert lib.at_serve(C.byref(sc), reqs, 2, None, res, None) == atns.AT_E_INVAL
+    assert "sorted" in lib.at_last_error().decode()
+    reqs[1].arrival_s = 0.6
+    reqs[1].n, reqs[1].p = 18, 4  # 18 is not a multiple of 4
+    assert lib.at_serve(C.byref(sc), reqs, 2, None, res, None) == atns.AT_E_INVAL
+    bad = atns._ServeConfig(atns.FP32, 0, -1, 64, 1e9)
+    assert lib.at_serve(C.byref(bad), reqs, 0, None, res, None) == atns.AT_E_INVAL
