@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the same workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-run workload")
@@ -89,7 +89,7 @@ def time_steps(torch, sim, warmup, steps):
     return ms, kt
 
 
-STAGE_KERNELS = ("k_stage", "k_ghost_views")
+STAGE_KERNELS = ("k_stage", "k_at_sums")
 
 
 def roofline(kt, n, pe, word, pd, steps):

@@ -233,10 +233,10 @@ uint64_t splitmix64(uint64_t seed, uint64_t counter) {
 }
 
 template <typename T>
-hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode) {
+hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode, bool at) {
   const int id = mode == kModeStepH ? kKStage : (mode == kModeRhsH ? kKRhs : kKPublish);
   if (s->timer) s->timer->before(id, s->stream);
-  hipError_t e = launch_fused<T>(a, s->tile, s->zchunk, mode, s->stream);
+  hipError_t e = launch_fused<T>(a, s->tile, s->zchunk, mode, at, s->stream);
   if (s->timer) s->timer->after(id, s->stream);
   return e;
 }
@@ -244,7 +244,7 @@ hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode) {
 template <typename T>
 hipError_t launch_views(at_sim* s, const StageArgs<T>& a) {
   if (s->timer) s->timer->before(kKGhost, s->stream);
-  hipError_t e = launch_ghost_views<T>(a, s->stream);
+  hipError_t e = launch_at_sums<T>(a, s->stream);
   if (s->timer) s->timer->after(kKGhost, s->stream);
   return e;
 }
@@ -279,7 +279,7 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
       a.step_mod_r = (int)(lev % s->g.R);
       a.cstage = T(0);
       a.publish = 1;
-      HIP_TRY(launch_hooked<T>(s, a, kModePublishH));
+      HIP_TRY(launch_hooked<T>(s, a, kModePublishH, false));
     }
   }
   HIP_TRY(hipMemsetAsync(s->ws + s->L.dq, 0, sizeof(T) * kNQ * N, s->stream));
@@ -321,7 +321,7 @@ int do_steps(at_sim* s, int nsteps) {
       a.publish = st == 0;
       a.store_dq = st < 2;
       if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
-      HIP_TRY(launch_hooked<T>(s, a, kModeStepH));
+      HIP_TRY(launch_hooked<T>(s, a, kModeStepH, s->step_delayed[(size_t)s->step] != 0));
       s->qcur = 1 - s->qcur;
     }
     s->step++;
@@ -348,7 +348,7 @@ int do_rhs(at_sim* s, void* out) {
     a.force.table = tab;
   }
   if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
-  HIP_TRY(launch_hooked<T>(s, a, kModeRhsH));
+  HIP_TRY(launch_hooked<T>(s, a, kModeRhsH, s->step_delayed[(size_t)s->step] != 0));
   return AT_OK;
 }
 

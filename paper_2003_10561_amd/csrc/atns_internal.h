@@ -64,7 +64,7 @@ struct StageArgs {
   T* q_out;           // conserved state written by the stage (the other buffer)
   T* dq;              // RK register [5][N]
   T* ring;            // ring base
-  T* gv_out;          // AT views of the face layers for this stage (written by k_ghost_views)
+  T* gv_out;          // AT sums of the face-layer readers for this stage (written by k_at_sums)
   const T* gv;        // the same buffer, read by the stage kernel
   T* rhs_out;         // RHS-only mode output [5][N] (null in stepping mode)
   const int8_t* delays;  // [ntiles][6] for this step
@@ -98,10 +98,11 @@ __host__ __device__ inline int tile_by(int t) { return tile_shape(t).by; }
 int64_t fused_blocks(const Geom& g, int tile, int zchunk);
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per compute unit on gfx950
 size_t fused_lds_bytes(int tile, size_t word, bool forced);
+// `at`: some face of the run is delayed at this stage (selects the instantiation with the AT logic).
 template <typename T>
-hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, hipStream_t stream);
+hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, bool at, hipStream_t stream);
 template <typename T>
-hipError_t launch_ghost_views(const StageArgs<T>& a, hipStream_t stream);
+hipError_t launch_at_sums(const StageArgs<T>& a, hipStream_t stream);
 
 // Batched launches (one launch over the workgroups of many runs).  A run table is an array of
 // batch_arg_bytes<T>() records written by pack_batch_arg; work lists hold (run, local block).
@@ -110,11 +111,11 @@ size_t batch_arg_bytes();
 template <typename T>
 void pack_batch_arg(const StageArgs<T>& s, int tile, int zchunk, int views, void* dst);
 template <typename T>
-hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, int mode,
-                              hipStream_t stream);
+hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, bool publish,
+                              bool at, int mode, hipStream_t stream);
 template <typename T>
-hipError_t launch_views_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream);
-int64_t view_blocks(const Geom& g);  // 256-point blocks of k_ghost_views for one run
+hipError_t launch_at_sums_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream);
+int64_t view_blocks(const Geom& g);  // 256-point blocks of k_at_sums for one run
 constexpr int kModeStepH = 0, kModeRhsH = 1, kModePublishH = 2;
 
 // Kernel identities for timing (names in kernel_name()).

@@ -35,7 +35,7 @@ struct FArgs {
   T* q_out;
   T* dq;
   T* ring;
-  const T* gv;         // AT views of the face layers for this stage (one ring slot's layout)
+  const T* gv;         // AT sums of the face-layer readers for this stage (one ring slot's layout)
   T* rhs_out;
   const int8_t* delays;
   const T* ftab;
@@ -49,7 +49,7 @@ struct FArgs {
   int nx, ny, nz, px, py, ex, ey, ez;
   int R, step_mod_r, npair, zchunk, publish, store_dq;
   int gbx, gby;  // workgroups along x and y (a batched launch decodes its local block with them)
-  int views;     // batched ghost views: does this run read delayed levels at this stage
+  int views;     // batched AT sums: does this run read delayed levels at this stage
   T i12x, i12y, i12z, gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
   T cstage, rk_a, rk_b, dt;
   double vol;
@@ -98,13 +98,24 @@ __device__ __forceinline__ uint32_t slab_size(const FArgs<T>& a, int d) {
   return d == 0 ? a.slab0 : (d == 1 ? a.slab1 : a.slab2);
 }
 
-// AT value of ring component `comp` (0..3 primitives u, v, w, T; 4..8 face-normal flux) of a face
-// layer point at ring offset `off`, as seen from across its face at this stage: precomputed by
-// k_ghost_views (the extrapolation sum_l w_l(k + c) v^{n-k-l} with the reading PE's delay k).
+// AT sum of component `comp` (0..3 primitives u, v, w, T; 4..8 face-normal flux) for the reader
+// at face-layer ring offset `off`: the sum over the reader's stencil offsets m that cross its
+// delayed face of a_m view(X + m), precomputed for this stage by k_at_sums.
 template <typename T>
-__device__ __forceinline__ T ghost(const FArgs<T>& a, int d, int comp, uint32_t off, int k) {
-  (void)k;
+__device__ __forceinline__ T at_sum(const FArgs<T>& a, int d, int comp, uint32_t off) {
   return a.gv[off + (uint32_t)comp * slab_size(a, d)];
+}
+
+// Numerators a_m of the (1,4) first-derivative stencil at offsets m = -2, -1, +1, +2 (index mi);
+// the derivative is (sum_m a_m v(X + m)) / 12h.
+template <typename T>
+__device__ __forceinline__ constexpr T stencil_a(int mi) {
+  return mi == 0 ? T(1) : mi == 1 ? T(-8) : mi == 2 ? T(8) : T(-1);
+}
+
+// Bit mi set: offset m(mi) of a point at local index l in a PE of edge e >= 4 crosses a PE face.
+__device__ __forceinline__ int crossing_mask(int l, int e) {
+  return (l == 0 ? 0x3 : l == 1 ? 0x1 : 0) | (l == e - 1 ? 0xC : l == e - 2 ? 0x8 : 0);
 }
 
 // Primitives from conserved values: rho, u, v, w, T.
@@ -156,12 +167,93 @@ __device__ __forceinline__ void add5(T acc[kNQ], int c, T val) {
   }
 }
 
+// Per-column window of the z march: u, v, w, T of planes zc-2 .. zc+2 (index j = 0 .. 4) and rho,
+// E of plane zc, for the current plane zc; push() brings in plane zc + 3 and advances zc.  FP32
+// keeps it in registers (shifted one plane per push), FP64 in a thread-private LDS ring (slot z
+// mod 5, z mod 3), where registers are scarcer.
+template <typename T, int NCOL, bool REG>
+struct ZWin;
+
+template <typename T, int NCOL>
+struct ZWin<T, NCOL, true> {
+  T w[4][5], re[2][3];
+  __device__ __forceinline__ void init(T (*)[NCOL], int, int) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) w[c][j] = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) re[0][j] = re[1][j] = T(0);
+  }
+  __device__ __forceinline__ void fill(int j, T u, T v, T ww, T t) {
+    w[0][j] = u;
+    w[1][j] = v;
+    w[2][j] = ww;
+    w[3][j] = t;
+  }
+  __device__ __forceinline__ void fill_re(int j, T r, T e) {
+    re[0][j] = r;
+    re[1][j] = e;
+  }
+  __device__ __forceinline__ T get(int c, int j) const { return w[c][j]; }
+  __device__ __forceinline__ T rho() const { return re[0][0]; }
+  __device__ __forceinline__ T E() const { return re[1][0]; }
+  __device__ __forceinline__ void push(T u, T v, T ww, T t, T r, T e) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[c][j] = w[c][j + 1];
+    fill(4, u, v, ww, t);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[0][j] = re[0][j + 1];
+      re[1][j] = re[1][j + 1];
+    }
+    fill_re(2, r, e);
+  }
+};
+
+template <typename T, int NCOL>
+struct ZWin<T, NCOL, false> {
+  T (*s)[NCOL];  // [26][NCOL]: 5 c + slot for u, v, w, T; 20 + 3 (c - 4) + slot for rho, E
+  int wc, sb, sr;
+  __device__ __forceinline__ int s5(int j) const { return sb + j >= 5 ? sb + j - 5 : sb + j; }
+  __device__ __forceinline__ int s3(int j) const { return sr + j >= 3 ? sr + j - 3 : sr + j; }
+  __device__ __forceinline__ void init(T (*lds)[NCOL], int col, int zc) {
+    s = lds;
+    wc = col;
+    sb = pmod(zc - 2, 5);
+    sr = pmod(zc, 3);
+  }
+  __device__ __forceinline__ void fill(int j, T u, T v, T ww, T t) {
+    s[0 + s5(j)][wc] = u;
+    s[5 + s5(j)][wc] = v;
+    s[10 + s5(j)][wc] = ww;
+    s[15 + s5(j)][wc] = t;
+  }
+  __device__ __forceinline__ void fill_re(int j, T r, T e) {
+    s[20 + s3(j)][wc] = r;
+    s[23 + s3(j)][wc] = e;
+  }
+  __device__ __forceinline__ T get(int c, int j) const { return s[5 * c + s5(j)][wc]; }
+  __device__ __forceinline__ T rho() const { return s[20 + sr][wc]; }
+  __device__ __forceinline__ T E() const { return s[23 + sr][wc]; }
+  __device__ __forceinline__ void push(T u, T v, T ww, T t, T r, T e) {
+    fill(0, u, v, ww, t);  // plane zc + 3 takes the slot of plane zc - 2
+    fill_re(0, r, e);      // and of plane zc
+    sb = s5(1);
+    sr = s3(1);
+  }
+};
+
 // window element of component c (0 u, 1 v, 2 w, 3 T) at plane index j (plane zc - 2 + j)
-#define WIN(c, j) s_win[5 * (c) + sl5[j]][wc]
+#define WIN(c, j) zw.get(c, j)
 
 // One workgroup of a stage: the BX x BY column tile (bkx, bky) and z chunk bkz of run `a`; `blk`
-// is its slot among the run's workgroups for the FP64 totals.
-template <typename T, int BX, int BY>
+// is its slot among the run's workgroups for the FP64 totals.  PUB: this stage publishes the face
+// layers (stage 1 of a step, or a history level); AT: some face of the run is delayed at this
+// stage.  Each is compiled out of the stages that do not need it.
+template <typename T, int BX, int BY, bool PUB, bool AT>
 __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, const int bkx, const int bky,
                                            const int bkz, const uint32_t blk) {
   using TL = Tile<BX, BY>;
@@ -170,9 +262,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   __shared__ T s_fx[2][5][BY][BX + 4];   // F_x on the tile rows, x halo 2
   __shared__ T s_fy[2][5][BY + 4][BX];   // F_y on the tile columns, y halo 2
   __shared__ double s_tsum[kNQ][TL::NOWN];  // FP64 running sums of dQ per tile column
-  // per-column window of the z march (thread-private): u, v, w, T of 5 planes (ring slot
-  // z mod 5, index 5 c + slot) and rho, E of 3 planes (index 20 + 3 (c - 4) + z mod 3)
-  __shared__ T s_win[26][TL::NCOL];
+  constexpr bool kRegWin = sizeof(T) == 4;
+  __shared__ T s_win[kRegWin ? 1 : 26][kRegWin ? 1 : TL::NCOL];
   extern __shared__ unsigned char s_dyn[];  // forcing coefficients when forced
   T* s_force = reinterpret_cast<T*>(s_dyn);
 
@@ -228,6 +319,15 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   const bool near_x = lxe < 2 || lxe >= a.ex - 2;
   const bool near_y = lye < 2 || lye >= a.ey - 2;
   const uint32_t col = (uint32_t)gy * nx + gx;
+  // this column's face-layer ring offsets (less the z term), where it publishes and where its AT
+  // sums are: layer index jp = 4 t + (l < 2 ? l : l - e + 4)
+  const int jx = 4 * tx + (lxe < 2 ? lxe : lxe - a.ex + 4), jy = 4 * ty + (lye < 2 ? lye : lye - a.ey + 4);
+  const uint32_t zsx = (uint32_t)ny * (uint32_t)(4 * a.px), zsy = (uint32_t)(4 * a.py) * (uint32_t)nx;
+  const uint32_t opx = (uint32_t)gy * (uint32_t)(4 * a.px) + (uint32_t)jx;    // + z zsx
+  const uint32_t opy = a.rdir1 + (uint32_t)jy * (uint32_t)nx + (uint32_t)gx;  // + z zsy
+  // AT by masked stencil coefficients: where this column's PE face is delayed (k >= 1) the
+  // offsets that cross it get coefficient 0 and the reader adds its precomputed AT sum
+  const int cxm = crossing_mask(lxe, a.ex), cym = crossing_mask(lye, a.ey);
   const T* __restrict__ qin = a.q;
   const T inv_cv = a.inv_cv;
 
@@ -279,7 +379,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   for (int j = 0; j < 5; ++j)
 #pragma unroll
     for (int c = 0; c < kNQ; ++c) acc[j][c] = T(0);
-  const int wc = column ? tid : 0;
+  ZWin<T, kRegWin ? 1 : TL::NCOL, kRegWin> zw;
+  zw.init(s_win, column ? tid : 0, z0 - 2);
   if (column) {
     // planes z0-4 .. z0-1 into the window; z0 arrives through `raw`
 #pragma unroll
@@ -290,13 +391,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
 #pragma unroll
       for (int c = 0; c < 5; ++c) q[c] = qin[c * N + i];
       prim_of<T>(q, inv_cv, r_, u_, v_, w_, t_);
-      const int s5 = pmod(z, 5), s3 = pmod(z, 3);
-      s_win[0 + s5][wc] = u_;
-      s_win[5 + s5][wc] = v_;
-      s_win[10 + s5][wc] = w_;
-      s_win[15 + s5][wc] = t_;
-      s_win[20 + s3][wc] = r_;
-      s_win[23 + s3][wc] = q[4];
+      zw.fill(j - 1, u_, v_, w_, t_);
+      if (j >= 3) zw.fill_re(j - 3, r_, q[4]);
     }
     const uint32_t i0 = (uint32_t)pmod(z0, nz) * plane + col;
 #pragma unroll
@@ -311,24 +407,18 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   if (column) {
     T r_, u_, v_, w_, t_;
     prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
-    const int s5 = pmod(z0, 5), s3 = pmod(z0, 3);
-    s_win[0 + s5][wc] = u_;
-    s_win[5 + s5][wc] = v_;
-    s_win[10 + s5][wc] = w_;
-    s_win[15 + s5][wc] = t_;
-    s_win[20 + s3][wc] = r_;
-    s_win[23 + s3][wc] = raw[4];
+    zw.fill(4, u_, v_, w_, t_);
+    zw.fill_re(2, r_, raw[4]);
     if (z0 + 1 <= z1 + 3) {
       const uint32_t i = (uint32_t)pmod(z0 + 1, nz) * plane + col;
 #pragma unroll
       for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
     }
-    const int sp = pmod(z0 - 2, 5);
     const int b0 = z0 & 1;
-    s_pr[b0][0][py][px] = s_win[0 + sp][wc];
-    s_pr[b0][1][py][px] = s_win[5 + sp][wc];
-    s_pr[b0][2][py][px] = s_win[10 + sp][wc];
-    s_pr[b0][3][py][px] = s_win[15 + sp][wc];
+    s_pr[b0][0][py][px] = zw.get(0, 2);
+    s_pr[b0][1][py][px] = zw.get(1, 2);
+    s_pr[b0][2][py][px] = zw.get(2, 2);
+    s_pr[b0][3][py][px] = zw.get(3, 2);
   }
   if (ex_ >= 0) {
     T xr, xu, xv, xw, xt;
@@ -344,10 +434,44 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   }
   __syncthreads();
 
-  // delays of this column's PE, cached per z-PE: the x / y face delays this column's stencils can
-  // cross (0 away from those faces), and both z-face delays; the previous plane's x / y delays are
-  // kept for its divergence, which runs one plane behind
-  int tz_c = -1, kcx = 0, kcy = 0, kzl = 0, kzh = 0;
+  // Delays of this column's PE, cached per z-PE: the x / y face delays its stencils can cross (0
+  // away from those faces) with the masked x / y stencil coefficients, and both z-face delays; for
+  // plane zc (gradients) and, one plane behind, zc - 1 (divergence).  The AT sums the column reads
+  // are loaded one iteration ahead (vx, vy: gradients of plane zc; vfx, vfy: divergence of plane
+  // zc - 1), so that their latency overlaps a whole plane of work.
+  int tz_c = -1, kcx = 0, kcy = 0, kzl = 0, kzh = 0, kcx_d = 0, kcy_d = 0;
+  T bx[4], by[4], bxd[4], byd[4], vx[4], vy[4];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi) {
+    bx[mi] = by[mi] = bxd[mi] = byd[mi] = stencil_a<T>(mi);
+    vx[mi] = vy[mi] = T(0);
+  }
+  auto plane_delays = [&](int zpl) {
+    if (!AT) return;
+    const int gzp = pmod(zpl, nz), tzp = gzp / a.ez;
+    if (column && tzp != tz_c) {
+      tz_c = tzp;
+      const int8_t* kf = a.delays + ((tzp * a.py + ty) * a.px + tx) * 6;
+      kcx = near_x ? (lxe < 2 ? kf[0] : kf[1]) : 0;
+      kcy = near_y ? (lye < 2 ? kf[2] : kf[3]) : 0;
+      kzl = kf[4];
+      kzh = kf[5];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) {
+        bx[mi] = (kcx > 0 && ((cxm >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
+        by[mi] = (kcy > 0 && ((cym >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
+      }
+    }
+    if (__builtin_expect(kcx > 0, 0)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vx[c] = at_sum<T>(a, 0, c, (uint32_t)gzp * zsx + opx);
+    }
+    if (__builtin_expect(kcy > 0, 0)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vy[c] = at_sum<T>(a, 1, c, (uint32_t)gzp * zsy + opy);
+    }
+  };
+  plane_delays(z0 - 2);
 
   // Iteration zc: fluxes of plane zc (LDS buffers of parity zc), x-y divergence of plane zc - 1,
   // update of plane zc - 2, then the window and LDS plane for zc + 1; one barrier per plane.
@@ -356,16 +480,20 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     const int gz = pmod(zc, nz);
     const int tz = gz / a.ez;
     const int lze = gz - tz * a.ez;
-    const int kcx_d = kcx, kcy_d = kcy;
-    if (column && tz != tz_c) {
-      tz_c = tz;
-      const int8_t* kf = a.delays + ((tz * a.py + ty) * a.px + tx) * 6;
-      kcx = near_x ? (lxe < 2 ? kf[0] : kf[1]) : 0;
-      kcy = near_y ? (lye < 2 ? kf[2] : kf[3]) : 0;
-      kzl = kf[4];
-      kzh = kf[5];
+    const int kcz = !AT ? 0 : lze < 2 ? kzl : (lze >= a.ez - 2 ? kzh : 0);
+    T vfx[kNQ], vfy[kNQ];
+#pragma unroll
+    for (int c = 0; c < kNQ; ++c) vfx[c] = vfy[c] = T(0);
+    if (__builtin_expect(valid && kcx_d > 0, 0)) {
+      const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsx + opx;
+#pragma unroll
+      for (int c = 0; c < kNQ; ++c) vfx[c] = at_sum<T>(a, 0, 4 + c, o);
     }
-    const int kcz = lze < 2 ? kzl : (lze >= a.ez - 2 ? kzh : 0);
+    if (__builtin_expect(valid && kcy_d > 0, 0)) {
+      const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsy + opy;
+#pragma unroll
+      for (int c = 0; c < kNQ; ++c) vfy[c] = at_sum<T>(a, 1, 4 + c, o);
+    }
     const bool zin = zc >= z0 && zc < z1;
     const bool zin_d = zc - 1 >= z0 && zc - 1 < z1;
     const int gzd = pmod(zc - 1, nz);
@@ -382,77 +510,51 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         for (int c = 0; c < 5; ++c) fd[c] = a.dq[c * N + fi];
       }
     }
-    // ring slots of planes zc-2 .. zc+2 (u, v, w, T) and zc (rho, E)
-    const int sb = pmod(zc - 2, 5);
-    int sl5[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) sl5[j] = sb + j >= 5 ? sb + j - 5 : sb + j;
-    const int sr = pmod(zc, 3);
 
     // fluxes of this column at plane zc: the tile computes all three (F_z also just outside the
     // chunk, for the z divergence), the halo rows F_y and the halo columns F_x
-    const bool pub = valid && zin && a.publish;
+    const bool pub = PUB && valid && zin;
     const bool need_fx = (role == 0 || role == 2) && zin && mode != kModePublish;
     const bool need_fy = (role == 0 || role == 1) && zin && mode != kModePublish;
     const bool need_fz = valid && mode != kModePublish;
     if (need_fx || need_fy || need_fz || pub) {
       T G[kNGrad];
-      // central derivatives of u, v, w, T: x and y from the LDS plane, z from the window
+      // derivatives of u, v, w, T: x and y from the LDS plane, z from the window.  Where a stencil
+      // crosses a delayed face the points across carry coefficient 0 and the reader's AT sum
+      // replaces them; elsewhere the central form is the same expression in every instantiation
+      // (so a run's result does not depend on whether another run of its batch is delayed)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        set_grad(G, c, 0, (s_pr[bc][c][py][px - 2] - T(8) * s_pr[bc][c][py][px - 1] +
-                           T(8) * s_pr[bc][c][py][px + 1] - s_pr[bc][c][py][px + 2]) * a.i12x);
-        set_grad(G, c, 1, (s_pr[bc][c][py - 2][px] - T(8) * s_pr[bc][c][py - 1][px] +
-                           T(8) * s_pr[bc][c][py + 1][px] - s_pr[bc][c][py + 2][px]) * a.i12y);
+        const T xm2 = s_pr[bc][c][py][px - 2], xm1 = s_pr[bc][c][py][px - 1], xp1 = s_pr[bc][c][py][px + 1],
+                xp2 = s_pr[bc][c][py][px + 2];
+        const T ym2 = s_pr[bc][c][py - 2][px], ym1 = s_pr[bc][c][py - 1][px], yp1 = s_pr[bc][c][py + 1][px],
+                yp2 = s_pr[bc][c][py + 2][px];
+        T dx = xm2 - T(8) * xm1 + T(8) * xp1 - xp2;
+        T dy = ym2 - T(8) * ym1 + T(8) * yp1 - yp2;
+        if (__builtin_expect(kcx > 0, 0)) dx = bx[0] * xm2 + bx[1] * xm1 + bx[2] * xp1 + bx[3] * xp2 + vx[c];
+        if (__builtin_expect(kcy > 0, 0)) dy = by[0] * ym2 + by[1] * ym1 + by[2] * yp1 + by[3] * yp2 + vy[c];
+        set_grad(G, c, 0, dx * a.i12x);
+        set_grad(G, c, 1, dy * a.i12y);
         set_grad(G, c, 2, (WIN(c, 0) - T(8) * WIN(c, 1) + T(8) * WIN(c, 3) - WIN(c, 4)) * a.i12z);
       }
-      // a stencil that crosses a face with delay k >= 1 is recomputed with the AT values there
-      if (kcx > 0) {
+      if (__builtin_expect(kcz > 0, 0)) {
+        // near a delayed z face (the same for the whole plane unless the column's PEs differ)
+        const uint32_t oz = slab_off(a, 2, gx, gy, gz);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          T v[4];
-#pragma unroll
-          for (int mi = 0; mi < 4; ++mi) {
-            const int m = mi < 2 ? mi - 2 : mi - 1;
-            const int l = lxe + m;
-            v[mi] = (l < 0 || l >= a.ex) ? ghost<T>(a, 0, c, slab_off(a, 0, pmod(gx + m, nx), gy, gz), kcx)
-                                          : s_pr[bc][c][py][px + m];
-          }
-          set_grad(G, c, 0, (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12x);
-        }
-      }
-      if (kcy > 0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          T v[4];
-#pragma unroll
-          for (int mi = 0; mi < 4; ++mi) {
-            const int m = mi < 2 ? mi - 2 : mi - 1;
-            const int l = lye + m;
-            v[mi] = (l < 0 || l >= a.ey) ? ghost<T>(a, 1, c, slab_off(a, 1, gx, pmod(gy + m, ny), gz), kcy)
-                                          : s_pr[bc][c][py + m][px];
-          }
-          set_grad(G, c, 1, (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12y);
-        }
-      }
-      if (kcz > 0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          T v[4];
+          T dz = at_sum<T>(a, 2, c, oz);
 #pragma unroll
           for (int mi = 0; mi < 4; ++mi) {
             const int m = mi < 2 ? mi - 2 : mi - 1;
             const int l = lze + m;
-            v[mi] = (l < 0 || l >= a.ez) ? ghost<T>(a, 2, c, slab_off(a, 2, gx, gy, pmod(gz + m, nz)), kcz)
-                                          : WIN(c, 2 + m);
+            if (l >= 0 && l < a.ez) dz += stencil_a<T>(mi) * WIN(c, 2 + m);
           }
-          set_grad(G, c, 2, (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12z);
+          set_grad(G, c, 2, dz * a.i12z);
         }
       }
       // stress, pressure and the total fluxes (Eqs. cont, mome, ie in total-energy form), one
       // direction at a time
-      const T rho = s_win[20 + sr][wc], u = WIN(0, 2), v = WIN(1, 2), w = WIN(2, 2), t = WIN(3, 2),
-              E = s_win[23 + sr][wc];
+      const T rho = zw.rho(), u = WIN(0, 2), v = WIN(1, 2), w = WIN(2, 2), t = WIN(3, 2), E = zw.E();
       const T mu = visc<T>(a, t);
       const T kt = mu * a.cp_over_pr;
       const T th = G[0] + G[4] + G[8];
@@ -482,7 +584,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         }
         if (pubx) {
           const uint32_t sl = a.slab0;
-          T* b = rb + slab_off(a, 0, gx, gy, gz);
+          T* b = rb + ((uint32_t)gz * zsx + opx);
           b[0] = u;
           b[sl] = v;
           b[2 * sl] = w;
@@ -504,7 +606,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         }
         if (puby) {
           const uint32_t sl = a.slab1;
-          T* b = rb + slab_off(a, 1, gx, gy, gz);
+          T* b = rb + ((uint32_t)gz * zsy + opy);
           b[0] = u;
           b[sl] = v;
           b[2 * sl] = w;
@@ -533,7 +635,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         if (need_fz) {
           // scatter F_z(zc) into the receivers zc + r (RHS -= D_z F_z).  The source sits at
           // offset m = -r from receiver zc + r; a receiver in another z-PE whose face is delayed
-          // reads the extrapolated flux instead (the receiver's PE owns that decision).
+          // takes no contribution from it and adds its AT sum instead when it is finalized (the
+          // receiver's PE owns that decision).
 #pragma unroll
           for (int ri = 0; ri < 4; ++ri) {
             const int r = ri < 2 ? ri - 2 : ri - 1;
@@ -545,14 +648,10 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
             const int tzp = gzp / a.ez;
             const int l = gzp - tzp * a.ez + m;
             int k = 0;
-            if (l < 0 || l >= a.ez) k = a.delays[((tzp * a.py + ty) * a.px + tx) * 6 + (l < 0 ? 4 : 5)];
+            if (AT && (l < 0 || l >= a.ez)) k = a.delays[((tzp * a.py + ty) * a.px + tx) * 6 + (l < 0 ? 4 : 5)];
             if (k == 0) {
 #pragma unroll
               for (int c = 0; c < kNQ; ++c) acc[2 + r][c] -= cm * F[c];
-            } else {
-              const uint32_t so = slab_off(a, 2, gx, gy, gz);
-#pragma unroll
-              for (int c = 0; c < kNQ; ++c) add5(acc[2 + r], c, -cm * ghost<T>(a, 2, 4 + c, so, k));
             }
           }
         }
@@ -563,46 +662,15 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       const int fxx = px - 2, fyy = py - 2;  // this point in s_fx (column) and s_fy (row)
 #pragma unroll
       for (int c = 0; c < kNQ; ++c) {
-        const T dfx = (s_fx[bd][c][py - 4][fxx - 2] - T(8) * s_fx[bd][c][py - 4][fxx - 1] + T(8) * s_fx[bd][c][py - 4][fxx + 1] -
-                       s_fx[bd][c][py - 4][fxx + 2]) * a.i12x;
-        const T dfy = (s_fy[bd][c][fyy - 2][px - 4] - T(8) * s_fy[bd][c][fyy - 1][px - 4] + T(8) * s_fy[bd][c][fyy + 1][px - 4] -
-                       s_fy[bd][c][fyy + 2][px - 4]) * a.i12y;
-        acc[1][c] -= dfx + dfy;
-      }
-      // stencils crossing a delayed face: replace the central value by the AT one
-      if (kcx_d > 0) {
-#pragma unroll
-        for (int c = 0; c < kNQ; ++c) {
-          T v[4];
-#pragma unroll
-          for (int mi = 0; mi < 4; ++mi) {
-            const int m = mi < 2 ? mi - 2 : mi - 1;
-            const int l = lxe + m;
-            v[mi] = (l < 0 || l >= a.ex) ? ghost<T>(a, 0, 4 + c, slab_off(a, 0, pmod(gx + m, nx), gy, gzd), kcx_d)
-                                          : s_fx[bd][c][py - 4][fxx + m];
-          }
-          const T cen = (s_fx[bd][c][py - 4][fxx - 2] - T(8) * s_fx[bd][c][py - 4][fxx - 1] + T(8) * s_fx[bd][c][py - 4][fxx + 1] -
-                         s_fx[bd][c][py - 4][fxx + 2]) * a.i12x;
-          const T at = (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12x;
-          add5(acc[1], c, cen - at);
-        }
-      }
-      if (kcy_d > 0) {
-#pragma unroll
-        for (int c = 0; c < kNQ; ++c) {
-          T v[4];
-#pragma unroll
-          for (int mi = 0; mi < 4; ++mi) {
-            const int m = mi < 2 ? mi - 2 : mi - 1;
-            const int l = lye + m;
-            v[mi] = (l < 0 || l >= a.ey) ? ghost<T>(a, 1, 4 + c, slab_off(a, 1, gx, pmod(gy + m, ny), gzd), kcy_d)
-                                          : s_fy[bd][c][fyy + m][px - 4];
-          }
-          const T cen = (s_fy[bd][c][fyy - 2][px - 4] - T(8) * s_fy[bd][c][fyy - 1][px - 4] + T(8) * s_fy[bd][c][fyy + 1][px - 4] -
-                         s_fy[bd][c][fyy + 2][px - 4]) * a.i12y;
-          const T at = (v[0] - T(8) * v[1] + T(8) * v[2] - v[3]) * a.i12y;
-          add5(acc[1], c, cen - at);
-        }
+        const T xm2 = s_fx[bd][c][py - 4][fxx - 2], xm1 = s_fx[bd][c][py - 4][fxx - 1],
+                xp1 = s_fx[bd][c][py - 4][fxx + 1], xp2 = s_fx[bd][c][py - 4][fxx + 2];
+        const T ym2 = s_fy[bd][c][fyy - 2][px - 4], ym1 = s_fy[bd][c][fyy - 1][px - 4],
+                yp1 = s_fy[bd][c][fyy + 1][px - 4], yp2 = s_fy[bd][c][fyy + 2][px - 4];
+        T dfx = xm2 - T(8) * xm1 + T(8) * xp1 - xp2;
+        T dfy = ym2 - T(8) * ym1 + T(8) * yp1 - yp2;
+        if (__builtin_expect(kcx_d > 0, 0)) dfx = bxd[0] * xm2 + bxd[1] * xm1 + bxd[2] * xp1 + bxd[3] * xp2 + vfx[c];
+        if (__builtin_expect(kcy_d > 0, 0)) dfy = byd[0] * ym2 + byd[1] * ym1 + byd[2] * yp1 + byd[3] * yp2 + vfy[c];
+        acc[1][c] -= dfx * a.i12x + dfy * a.i12y;
       }
     }
 
@@ -611,6 +679,20 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       T r[kNQ];
 #pragma unroll
       for (int c = 0; c < kNQ; ++c) r[c] = acc[0][c];
+      if (AT) {
+        // a plane next to a z face whose delay is k >= 1: the F_z values across it were left out
+        // of the scatter; add the AT sum (uniform across the plane but for the columns' PEs)
+        const int gzf = pmod(zf, nz);
+        const int tzf = gzf / a.ez, lzf = gzf - tzf * a.ez;
+        if (lzf < 2 || lzf >= a.ez - 2) {
+          const int k = a.delays[((tzf * a.py + ty) * a.px + tx) * 6 + (lzf < 2 ? 4 : 5)];
+          if (k > 0) {
+            const uint32_t oz = slab_off(a, 2, gx, gy, gzf);
+#pragma unroll
+            for (int c = 0; c < kNQ; ++c) r[c] -= at_sum<T>(a, 2, 4 + c, oz) * a.i12z;
+          }
+        }
+      }
       if (forced) {
         // f_c = 2 Re(sum_kz B_kz,c e^{i kz z}), B from LDS, e^{i kz z} for kz = 1, 2 from the table
         const int gzf = pmod(zf, nz);
@@ -652,25 +734,28 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     // prepare plane zc + 1: window gets plane zc + 3 (replacing zc - 2), LDS plane zc + 1
     if (zc <= z1) {
       const int bn = bd;  // parity of zc + 1
+      // the divergence of plane zc (next iteration) with this plane's delays; AT sums ahead
+      kcx_d = kcx;
+      kcy_d = kcy;
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) {
+        bxd[mi] = bx[mi];
+        byd[mi] = by[mi];
+      }
+      plane_delays(zc + 1);
       if (column) {
         T r_, u_, v_, w_, t_;
         prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
-        const int s3 = pmod(zc + 3, 3);
-        s_win[0 + sl5[0]][wc] = u_;
-        s_win[5 + sl5[0]][wc] = v_;
-        s_win[10 + sl5[0]][wc] = w_;
-        s_win[15 + sl5[0]][wc] = t_;
-        s_win[20 + s3][wc] = r_;
-        s_win[23 + s3][wc] = raw[4];
+        zw.push(u_, v_, w_, t_, r_, raw[4]);
         if (zc + 4 <= z1 + 3) {
           const uint32_t i = (uint32_t)pmod(zc + 4, nz) * plane + col;
 #pragma unroll
           for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
         }
-        s_pr[bn][0][py][px] = s_win[0 + sl5[3]][wc];
-        s_pr[bn][1][py][px] = s_win[5 + sl5[3]][wc];
-        s_pr[bn][2][py][px] = s_win[10 + sl5[3]][wc];
-        s_pr[bn][3][py][px] = s_win[15 + sl5[3]][wc];
+        s_pr[bn][0][py][px] = zw.get(0, 2);
+        s_pr[bn][1][py][px] = zw.get(1, 2);
+        s_pr[bn][2][py][px] = zw.get(2, 2);
+        s_pr[bn][3][py][px] = zw.get(3, 2);
       }
       if (ex_ >= 0) {
         T xr, xu, xv, xw, xt;
@@ -714,26 +799,30 @@ __device__ __forceinline__ uint32_t xcd_major(uint32_t w, uint32_t nb) {
 }
 
 // MINW: waves per SIMD the register allocation must allow (occupancy target).
-template <typename T, int BX, int BY, int MINW>
+template <typename T, int BX, int BY, int MINW, bool PUB, bool AT>
 __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, int mode) {
   const uint32_t gx = (uint32_t)a.gbx, gxy = gx * (uint32_t)a.gby;
   const uint32_t L = xcd_major(blockIdx.x, gridDim.x);
   const uint32_t bz = L / gxy, r = L - bz * gxy, by = r / gx, bx = r - by * gx;
-  stage_body<T, BX, BY>(a, mode, (int)bx, (int)by, (int)bz, L);
+  stage_body<T, BX, BY, PUB, AT>(a, mode, (int)bx, (int)by, (int)bz, L);
 }
 
 // Batched stage: one launch over the workgroups of many runs.  work[b] = (run, local workgroup);
 // the run's arguments come from the device run table, so each run sees exactly the workgroup
-// decomposition (and therefore the arithmetic) of its own single-run launch.
-template <typename T, int BX, int BY, int MINW>
+// decomposition (and therefore the arithmetic) of its own single-run launch.  A run executes in
+// the instantiation its own single-run step would use: the AT one where it reads delayed levels
+// at this stage (its `views` flag), the other one elsewhere; its workgroups leave the other
+// instantiation's launch at once.
+template <typename T, int BX, int BY, int MINW, bool PUB, bool AT>
 __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage_batch(const FArgs<T>* __restrict__ runs,
                                                                           const uint2* __restrict__ work,
                                                                           int mode) {
   const uint2 w = work[xcd_major(blockIdx.x, gridDim.x)];
   const FArgs<T> a = runs[w.x];
+  if ((a.views != 0) != AT) return;  // uniform across the workgroup
   const uint32_t per = (uint32_t)a.gbx * (uint32_t)a.gby;
   const uint32_t bz = w.y / per, r = w.y - bz * per, by = r / (uint32_t)a.gbx, bx = r - by * (uint32_t)a.gbx;
-  stage_body<T, BX, BY>(a, mode, (int)bx, (int)by, (int)bz, w.y);
+  stage_body<T, BX, BY, PUB, AT>(a, mode, (int)bx, (int)by, (int)bz, w.y);
 }
 
 template <typename T>
@@ -798,12 +887,13 @@ FArgs<T> pack(const StageArgs<T>& s, int zchunk) {
 template <typename T, int BX, int BY>
 constexpr size_t stage_static_lds() {
   using TL = Tile<BX, BY>;
-  return sizeof(T) * (2 * (4 * TL::LH * TL::LW + 5 * BY * (BX + 4) + 5 * (BY + 4) * BX) + 26 * TL::NCOL) +
+  return sizeof(T) * (2 * (4 * TL::LH * TL::LW + 5 * BY * (BX + 4) + 5 * (BY + 4) * BX) +
+                      (sizeof(T) == 4 ? 1 : 26 * TL::NCOL)) +
          8 * kNQ * TL::NOWN;
 }
 
 template <typename T, int BX, int BY, int MINW>
-hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, hipStream_t stream) {
+hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipStream_t stream) {
   if constexpr (stage_static_lds<T, BX, BY>() > kLdsBytes) {
     return hipErrorInvalidConfiguration;
   } else {
@@ -816,21 +906,33 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, hipStream_t s
     a.gbx = (int)gx;
     a.gby = (int)gy;
     const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
-    hipLaunchKernelGGL((k_stage<T, BX, BY, MINW>), dim3(gx * gy * gz), dim3(Tile<BX, BY>::NT), dyn, stream, a, mode);
+    const dim3 grid(gx * gy * gz), block(Tile<BX, BY>::NT);
+    if (s.publish && at)
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, true>), grid, block, dyn, stream, a, mode);
+    else if (s.publish)
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, false>), grid, block, dyn, stream, a, mode);
+    else if (at)
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, true>), grid, block, dyn, stream, a, mode);
+    else
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, false>), grid, block, dyn, stream, a, mode);
     return hipGetLastError();
   }
 }
 
-// AT views of all published face-layer points for one stage: for a point on layer 0/1 (2/3) of
-// PE t along d, the reader is the neighbouring PE t-1 (t+1) across that face; with its delay k > 0
-// the view is w_0 v^{n-k} + w_1 v^{n-k-1} + w_2 v^{n-k-2}, w from kappa = k + c_s (Sec. 2.1,
-// Eq. at; Appendix B weights at c_s = 0).  Points whose reader has k = 0 are not written.
+// AT sums of one stage, per reader (Sec. 2.1, Eq. at; Appendix B, (1,4) rows).  A point on face
+// layer l of PE t along d reads, across the face on its side (layers 0, 1: the lower face, read
+// from PE t-1; layers 2, 3: the upper face, from PE t+1), the stencil offsets m that leave its PE:
+// m = -2, -1 (l = 0), -2 (l = 1), +2 (l = 2), +1, +2 (l = 3).  With the reader PE's delay k >= 1 on
+// that face the value there is the extrapolation w_0 v^{n-k} + w_1 v^{n-k-1} + w_2 v^{n-k-2},
+// w from kappa = k + c_s (the Appendix B weights at c_s = 0); the kernel stores, for each of the 9
+// ring components, sum_m a_m (extrapolated value at X + m) at the reader's own ring offset, with
+// a = (1, -8, 8, -1) the stencil numerators.  Readers whose face has k = 0 are not written.
 template <typename T>
-__device__ __forceinline__ void ghost_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid) {
+__device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid) {
   const uint32_t total = a.slab0 + a.slab1 + a.slab2;
   if (tid >= total) return;
   int d, x, y, z, jp;
-  uint32_t sidx;
+  uint32_t sidx, jstride;  // slab index of the reader, stride of the layer index jp in it
   if (tid < a.slab0) {
     d = 0;
     sidx = tid;
@@ -840,6 +942,7 @@ __device__ __forceinline__ void ghost_body(const FArgs<T>& a, T* __restrict__ gv
     y = (int)(r % a.ny);
     z = (int)(r / a.ny);
     x = 0;
+    jstride = 1;
   } else if (tid < a.slab0 + a.slab1) {
     d = 1;
     sidx = tid - a.slab0;
@@ -848,6 +951,7 @@ __device__ __forceinline__ void ghost_body(const FArgs<T>& a, T* __restrict__ gv
     jp = (int)(r % (4 * a.py));
     z = (int)(r / (4 * a.py));
     y = 0;
+    jstride = (uint32_t)a.nx;
   } else {
     d = 2;
     sidx = tid - a.slab0 - a.slab1;
@@ -856,19 +960,23 @@ __device__ __forceinline__ void ghost_body(const FArgs<T>& a, T* __restrict__ gv
     y = (int)(r % a.ny);
     jp = (int)(r / a.ny);
     z = 0;
+    jstride = (uint32_t)a.nx * (uint32_t)a.ny;
   }
   const int t = jp / 4, layer = jp % 4;
-  // PE coordinates of the reader: the owner's neighbour across the nearest face along d
-  const int pz = a.nz / a.ez;
-  int rx = d == 0 ? 0 : x / a.ex, ry = d == 1 ? 0 : y / a.ey, rz = d == 2 ? 0 : z / a.ez;
-  const int pd = d == 0 ? a.px : (d == 1 ? a.py : pz);
-  const int rt = layer < 2 ? (t == 0 ? pd - 1 : t - 1) : (t == pd - 1 ? 0 : t + 1);
-  if (d == 0) rx = rt;
-  else if (d == 1) ry = rt;
-  else rz = rt;
-  const int face = 2 * d + (layer < 2 ? 1 : 0);
+  // the reader's PE: t along d, from the point's coordinates across
+  const int rx = d == 0 ? t : x / a.ex, ry = d == 1 ? t : y / a.ey, rz = d == 2 ? t : z / a.ez;
+  const int face = 2 * d + (layer < 2 ? 0 : 1);
   const int k = a.delays[((rz * a.py + ry) * a.px + rx) * 6 + face];
   if (k <= 0) return;
+  const int pd = d == 0 ? a.px : (d == 1 ? a.py : a.nz / a.ez);
+  const int tn = layer < 2 ? (t == 0 ? pd - 1 : t - 1) : (t == pd - 1 ? 0 : t + 1);
+  // crossing offsets of this layer: (source layer in PE tn, stencil numerator)
+  int ns = 0, sl0 = 0, sl1 = 0;
+  T a0 = T(0), a1 = T(0);
+  if (layer == 0) { ns = 2; sl0 = 2; a0 = T(1); sl1 = 3; a1 = T(-8); }
+  else if (layer == 1) { ns = 1; sl0 = 3; a0 = T(1); }
+  else if (layer == 2) { ns = 1; sl0 = 0; a0 = T(-1); }
+  else { ns = 2; sl0 = 0; a0 = T(8); sl1 = 1; a1 = T(-1); }
   const T kap = T(k) + a.cstage;
   const T w0 = (kap + T(1)) * (kap + T(2)) * T(0.5);
   const T w1 = -kap * (kap + T(2));
@@ -877,44 +985,53 @@ __device__ __forceinline__ void ghost_body(const FArgs<T>& a, T* __restrict__ gv
   s0 += s0 < 0 ? a.R : 0;
   const int s1 = s0 == 0 ? a.R - 1 : s0 - 1;
   const int s2 = s1 == 0 ? a.R - 1 : s1 - 1;
-  const uint32_t base = (d == 0 ? 0u : (d == 1 ? a.rdir1 : a.rdir2)) + sidx;
+  const uint32_t base = d == 0 ? 0u : (d == 1 ? a.rdir1 : a.rdir2);
   const uint32_t ss = d == 0 ? a.slab0 : (d == 1 ? a.slab1 : a.slab2);
+  const uint32_t src0 = base + sidx + (uint32_t)(4 * tn + sl0 - jp) * jstride;
+  const uint32_t src1 = base + sidx + (uint32_t)(4 * tn + sl1 - jp) * jstride;
+  const T* r0 = a.ring + (uint32_t)s0 * a.rslot;
+  const T* r1 = a.ring + (uint32_t)s1 * a.rslot;
+  const T* r2 = a.ring + (uint32_t)s2 * a.rslot;
 #pragma unroll
   for (int c = 0; c < kNRing; ++c) {
-    const uint32_t o = base + (uint32_t)c * ss;
-    gv[o] = w0 * a.ring[(uint32_t)s0 * a.rslot + o] + w1 * a.ring[(uint32_t)s1 * a.rslot + o] +
-            w2 * a.ring[(uint32_t)s2 * a.rslot + o];
+    const uint32_t o0 = src0 + (uint32_t)c * ss;
+    T v = a0 * (w0 * r0[o0] + w1 * r1[o0] + w2 * r2[o0]);
+    if (ns == 2) {
+      const uint32_t o1 = src1 + (uint32_t)c * ss;
+      v += a1 * (w0 * r0[o1] + w1 * r1[o1] + w2 * r2[o1]);
+    }
+    gv[base + sidx + (uint32_t)c * ss] = v;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_ghost_views(FArgs<T> a, T* __restrict__ gv) {
-  ghost_body<T>(a, gv, blockIdx.x * 256u + threadIdx.x);
+__global__ __launch_bounds__(256) void k_at_sums(FArgs<T> a, T* __restrict__ gv) {
+  at_sums_body<T>(a, gv, blockIdx.x * 256u + threadIdx.x);
 }
 
 // Batched views: work[b] = (run, local block of 256 face-layer points); runs that read no
 // delayed level at this stage leave at once.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ghost_views_batch(const FArgs<T>* __restrict__ runs,
+__global__ __launch_bounds__(256) void k_at_sums_batch(const FArgs<T>* __restrict__ runs,
                                                            const uint2* __restrict__ work) {
   const uint2 w = work[blockIdx.x];
   const FArgs<T> a = runs[w.x];
   if (!a.views) return;
-  ghost_body<T>(a, const_cast<T*>(a.gv), w.y * 256u + threadIdx.x);
+  at_sums_body<T>(a, const_cast<T*>(a.gv), w.y * 256u + threadIdx.x);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_ghost_views(const StageArgs<T>& a, hipStream_t stream) {
+hipError_t launch_at_sums(const StageArgs<T>& a, hipStream_t stream) {
   const Geom& g = a.g;
   const int64_t total = g.slab[0] + g.slab[1] + g.slab[2];
-  hipLaunchKernelGGL(k_ghost_views<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+  hipLaunchKernelGGL(k_at_sums<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
                      pack<T>(a, 4), a.gv_out);
   return hipGetLastError();
 }
-template hipError_t launch_ghost_views<double>(const StageArgs<double>&, hipStream_t);
-template hipError_t launch_ghost_views<float>(const StageArgs<float>&, hipStream_t);
+template hipError_t launch_at_sums<double>(const StageArgs<double>&, hipStream_t);
+template hipError_t launch_at_sums<float>(const StageArgs<float>&, hipStream_t);
 
 int64_t fused_blocks(const Geom& g, int tile, int zchunk) {
   const int bx = tile_bx(tile), by = tile_by(tile);
@@ -940,22 +1057,22 @@ size_t fused_lds_bytes(int tile, size_t word, bool forced) {
 }
 
 template <typename T>
-hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, hipStream_t stream) {
+hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, bool at, hipStream_t stream) {
   if (fused_lds_bytes(tile, sizeof(T), a.force.table != nullptr) > kLdsBytes) return hipErrorInvalidConfiguration;
   constexpr bool f32 = sizeof(T) == 4;
   switch (tile) {
-    case 0: return launch_cfg<T, 64, 8, f32 ? 4 : 2>(a, zchunk, mode, stream);
-    case 1: return launch_cfg<T, 32, 8, f32 ? 2 : 1>(a, zchunk, mode, stream);
-    case 2: return launch_cfg<T, 32, 8, f32 ? 4 : 2>(a, zchunk, mode, stream);
-    case 3: return launch_cfg<T, 32, 4, f32 ? 2 : 1>(a, zchunk, mode, stream);
-    case 4: return launch_cfg<T, 64, 4, f32 ? 3 : 2>(a, zchunk, mode, stream);
-    case 5: return launch_cfg<T, 16, 8, f32 ? 2 : 1>(a, zchunk, mode, stream);
+    case 0: return launch_cfg<T, 64, 8, f32 ? 4 : 2>(a, zchunk, mode, at, stream);
+    case 1: return launch_cfg<T, 32, 8, f32 ? 2 : 1>(a, zchunk, mode, at, stream);
+    case 2: return launch_cfg<T, 32, 8, f32 ? 4 : 2>(a, zchunk, mode, at, stream);
+    case 3: return launch_cfg<T, 32, 4, f32 ? 2 : 1>(a, zchunk, mode, at, stream);
+    case 4: return launch_cfg<T, 64, 4, f32 ? 3 : 2>(a, zchunk, mode, at, stream);
+    case 5: return launch_cfg<T, 16, 8, f32 ? 2 : 1>(a, zchunk, mode, at, stream);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_fused<double>(const StageArgs<double>&, int, int, int, hipStream_t);
-template hipError_t launch_fused<float>(const StageArgs<float>&, int, int, int, hipStream_t);
+template hipError_t launch_fused<double>(const StageArgs<double>&, int, int, int, bool, hipStream_t);
+template hipError_t launch_fused<float>(const StageArgs<float>&, int, int, int, bool, hipStream_t);
 
 template <typename T>
 size_t batch_arg_bytes() {
@@ -975,40 +1092,48 @@ int64_t view_blocks(const Geom& g) { return (g.slab[0] + g.slab[1] + g.slab[2] +
 
 namespace {
 template <typename T, int BX, int BY, int MINW>
-hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, bool forced, int mode,
-                            hipStream_t stream) {
+hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, bool forced, bool publish, bool at,
+                            int mode, hipStream_t stream) {
   if constexpr (stage_static_lds<T, BX, BY>() > kLdsBytes) {
     return hipErrorInvalidConfiguration;
   } else {
     const size_t dyn = forced ? sizeof(T) * 18 * BX * BY : 0;
-    hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW>), dim3((unsigned)nblk), dim3(Tile<BX, BY>::NT), dyn,
-                       stream, (const FArgs<T>*)runs, work, mode);
+    const dim3 grid((unsigned)nblk), block(Tile<BX, BY>::NT);
+    const FArgs<T>* r = (const FArgs<T>*)runs;
+    if (publish && at)
+      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, true>), grid, block, dyn, stream, r, work, mode);
+    else if (publish)
+      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, false>), grid, block, dyn, stream, r, work, mode);
+    else if (at)
+      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, true>), grid, block, dyn, stream, r, work, mode);
+    else
+      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, false>), grid, block, dyn, stream, r, work, mode);
     return hipGetLastError();
   }
 }
 }  // namespace
 
 template <typename T>
-hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, int mode,
-                              hipStream_t stream) {
+hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, bool publish,
+                              bool at, int mode, hipStream_t stream) {
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidValue;
   if (fused_lds_bytes(tile, sizeof(T), forced) > kLdsBytes) return hipErrorInvalidConfiguration;
   constexpr bool f32 = sizeof(T) == 4;
   switch (tile) {
-    case 0: return launch_batch_cfg<T, 64, 8, f32 ? 4 : 2>(runs, work, nblk, forced, mode, stream);
-    case 1: return launch_batch_cfg<T, 32, 8, f32 ? 2 : 1>(runs, work, nblk, forced, mode, stream);
-    case 2: return launch_batch_cfg<T, 32, 8, f32 ? 4 : 2>(runs, work, nblk, forced, mode, stream);
-    case 3: return launch_batch_cfg<T, 32, 4, f32 ? 2 : 1>(runs, work, nblk, forced, mode, stream);
-    case 4: return launch_batch_cfg<T, 64, 4, f32 ? 3 : 2>(runs, work, nblk, forced, mode, stream);
-    case 5: return launch_batch_cfg<T, 16, 8, f32 ? 2 : 1>(runs, work, nblk, forced, mode, stream);
+    case 0: return launch_batch_cfg<T, 64, 8, f32 ? 4 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
+    case 1: return launch_batch_cfg<T, 32, 8, f32 ? 2 : 1>(runs, work, nblk, forced, publish, at, mode, stream);
+    case 2: return launch_batch_cfg<T, 32, 8, f32 ? 4 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
+    case 3: return launch_batch_cfg<T, 32, 4, f32 ? 2 : 1>(runs, work, nblk, forced, publish, at, mode, stream);
+    case 4: return launch_batch_cfg<T, 64, 4, f32 ? 3 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
+    case 5: return launch_batch_cfg<T, 16, 8, f32 ? 2 : 1>(runs, work, nblk, forced, publish, at, mode, stream);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
-hipError_t launch_views_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream) {
+hipError_t launch_at_sums_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream) {
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ghost_views_batch<T>, dim3((unsigned)nblk), dim3(256), 0, stream, (const FArgs<T>*)runs,
+  hipLaunchKernelGGL(k_at_sums_batch<T>, dim3((unsigned)nblk), dim3(256), 0, stream, (const FArgs<T>*)runs,
                      work);
   return hipGetLastError();
 }
@@ -1017,9 +1142,9 @@ template size_t batch_arg_bytes<float>();
 template size_t batch_arg_bytes<double>();
 template void pack_batch_arg<float>(const StageArgs<float>&, int, int, int, void*);
 template void pack_batch_arg<double>(const StageArgs<double>&, int, int, int, void*);
-template hipError_t launch_fused_batch<float>(const void*, const uint2*, int64_t, int, bool, int, hipStream_t);
-template hipError_t launch_fused_batch<double>(const void*, const uint2*, int64_t, int, bool, int, hipStream_t);
-template hipError_t launch_views_batch<float>(const void*, const uint2*, int64_t, hipStream_t);
-template hipError_t launch_views_batch<double>(const void*, const uint2*, int64_t, hipStream_t);
+template hipError_t launch_fused_batch<float>(const void*, const uint2*, int64_t, int, bool, bool, bool, int, hipStream_t);
+template hipError_t launch_fused_batch<double>(const void*, const uint2*, int64_t, int, bool, bool, bool, int, hipStream_t);
+template hipError_t launch_at_sums_batch<float>(const void*, const uint2*, int64_t, hipStream_t);
+template hipError_t launch_at_sums_batch<double>(const void*, const uint2*, int64_t, hipStream_t);
 
 }  // namespace atns

@@ -22,7 +22,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 STAGE = "k_stage<"
-VIEWS = "k_ghost_views<"
+VIEWS = "k_at_sums<"
 
 
 def short_name(k):
@@ -51,12 +51,12 @@ def counters(pmc_dir):
 
 
 def timed_window(seq, timed):
-    """Entries from the `timed`-th last stage launch on (views launched before it included)."""
+    """Entries from the `timed`-th last stage launch on (its AT-sum launch included)."""
     idx = [i for i, (k, _) in enumerate(seq) if STAGE in k]
     if len(idx) < timed:
         raise ValueError(f"only {len(idx)} stage launches")
     first = idx[-timed]
-    # the face views of a delayed stage are launched just before its stage launch
+    # the AT sums of a delayed stage are launched just before its stage launch
     while first > 0 and VIEWS in seq[first - 1][0]:
         first -= 1
     last = idx[-1]
@@ -100,8 +100,8 @@ def main():
         lines.append(f"| `{short_name(k)[:80]}` | {c} | {t / c:.3f} | {t:.1f} |")
     lines += ["", f"Timed window (last {a.timed} stage launches):", "",
               f"- k_stage_avg_ms: {st_ms / a.timed:.4f}",
-              f"- k_ghost_views_launches: {n_gv}",
-              f"- k_ghost_views_ms_per_stage: {gv_ms / a.timed:.4f}",
+              f"- k_at_sums_launches: {n_gv}",
+              f"- k_at_sums_ms_per_stage: {gv_ms / a.timed:.4f}",
               f"- stage_avg_ms: {(st_ms + gv_ms) / a.timed:.4f}",
               f"- source_sha256: {source_sha()}", ""]
     with open(a.out + "_trace.md", "w") as f:
@@ -123,7 +123,7 @@ def main():
               f"Copy calibration: for a device copy of {a.copy_bytes:.0f} bytes each way, bytes moved / "
               f"bytes reported is {ff:.4f} for FETCH_SIZE and {fw:.4f} for WRITE_SIZE; these factors scale "
               "the stage counters below.", "",
-              "Per stage launch over the timed window (k_stage plus the AT face views of delayed stages):", "",
+              "Per stage launch over the timed window (k_stage plus the AT sums of delayed stages):", "",
               f"- fetch_bytes_per_launch: {fb:.6e}",
               f"- write_bytes_per_launch: {wb:.6e}",
               f"- bytes_per_launch: {fb + wb:.6e}",
