@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
     ap.add_argument("--zchunk", type=int, default=None)
+    ap.add_argument("--no-autotune", action="store_true", help="library default launch shape for the 512^3 runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-run workload")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the served request trace")
@@ -59,17 +60,28 @@ def parse():
     return ap.parse_args()
 
 
-def build_sim(atns, W, n, pe, precision, n_steps_total, q, dt, mu, fh, tile=None, zchunk=None):
+def build_sim(atns, W, n, pe, precision, n_steps_total, q, dt, mu, fh, tile=None, zchunk=None, autotune=True):
     cfg = atns.Config(n=(n, n, n), p=(pe, pe, pe), dt=dt, mu_ref=mu, max_delay=3,
                       precision=precision, forcing=True)
     sim = atns.Sim(cfg)
-    if tile is not None or zchunk is not None:
-        t0, z0 = sim.get_tuning()
-        sim.set_tuning(t0 if tile is None else tile, z0 if zchunk is None else zchunk)
     sim.init_field(q)
     sim.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=n_steps_total)
     sim.set_forcing(fh)
-    return sim
+    tuned = False
+    if tile is not None or zchunk is not None:
+        t0, z0 = sim.get_tuning()
+        sim.set_tuning(t0 if tile is None else tile, z0 if zchunk is None else zchunk)
+    elif autotune:
+        # the library's autotuner, through a batch of this one run (trial stages leave the state)
+        b = atns.Batch(precision)
+        b.add(sim)
+        b.autotune(None, reps=2)
+        t, z = b.get_tuning()
+        b.remove(sim)
+        b.close()
+        sim.set_tuning(t, z)
+        tuned = True
+    return sim, tuned
 
 
 def time_steps(torch, sim, warmup, steps):
@@ -164,6 +176,8 @@ def batch_specs(seed0=1000):
 def batched_workload(torch, atns, W, steps, warmup, cache):
     specs = batch_specs()
     sims = []
+    # the warm-up chunk has the timed chunk's length, so that the timed chunk replays its graph
+    warmup = steps
     total = warmup + steps + 1
     for sp in specs:
         n = sp["n"]
@@ -287,8 +301,9 @@ def main():
         sched[s] = s % 4
     pd = traffic.delayed_fraction(sched[Wm:Wm + K])
 
-    sim = build_sim(atns, W, n, pe, "fp32", total, q, dt, mu, fh, args.tile, args.zchunk)
-    log("fp32 simulation initialised; timing")
+    sim, tuned = build_sim(atns, W, n, pe, "fp32", total, q, dt, mu, fh, args.tile, args.zchunk, not args.no_autotune)
+    launch32 = {"tile": sim.get_tuning()[0], "zchunk": sim.get_tuning()[1], "autotuned": tuned}
+    log(f"fp32 simulation initialised (launch {launch32}); timing")
     ms32, kt32 = time_steps(torch, sim, Wm, K)
     st32 = sim.stats()
     del sim
@@ -304,11 +319,13 @@ def main():
                                   f"({n // pe}^3 each), CAA delays c_r=4 (L=3), OU forcing |k|<=2.5, "
                                   "FP32 fields / FP64 reductions, LS-RK3",
                       "n": n, "pe": [pe, pe, pe], "delays": "CAA L=3", "precision": "fp32"},
+           "launch": launch32,
            "roofline": rf,
            "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 4) * value / 1e9,
            "stats_after": {k: st32[k] for k in ("K", "eps", "enstrophy", "Mt", "nonfinite")}}
     if not args.no_fp64:
-        sim = build_sim(atns, W, n, pe, "fp64", total, q, dt, mu, fh, args.tile, args.zchunk)
+        sim, _ = build_sim(atns, W, n, pe, "fp64", total, q, dt, mu, fh, args.tile, args.zchunk, not args.no_autotune)
+        launch64 = {"tile": sim.get_tuning()[0], "zchunk": sim.get_tuning()[1]}
         log("fp64 simulation initialised; timing")
         ms64, kt64 = time_steps(torch, sim, Wm, K)
         st64 = sim.stats()
@@ -317,7 +334,7 @@ def main():
         log(f"fp64: {ms64 / K:.3f} ms/step")
         v64 = n ** 3 * K / (ms64 * 1e-3)
         rf64 = roofline(kt64, n, pe, 8, pd, K)
-        out["fp64"] = {"value": v64, "ms_per_step": ms64 / K, "roofline_frac": rf64["frac"],
+        out["fp64"] = {"value": v64, "ms_per_step": ms64 / K, "roofline_frac": rf64["frac"], "launch": launch64,
                        "achieved_gbs": rf64["achieved"],
                        "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 8) * v64 / 1e9,
                        "fp32_speedup": value / v64,
@@ -325,7 +342,7 @@ def main():
                                                   for k in ("K", "eps", "enstrophy", "Mt")}}
     if not args.no_batch:
         log("batched 64-run workload ...")
-        out["batched"] = batched_workload(torch, atns, W, args.batch_steps, 2, args.tune_cache)
+        out["batched"] = batched_workload(torch, atns, W, args.batch_steps, args.batch_steps, args.tune_cache)
         log(f"batched: {out['batched']}")
     if not args.no_serve:
         log("served trace ...")

@@ -218,12 +218,15 @@ ATNS_API int at_batch_step(at_batch* batch, int32_t n_steps);
 ATNS_API int at_batch_set_tuning(at_batch* batch, int32_t tile, int32_t zchunk);
 ATNS_API int at_batch_get_tuning(at_batch* batch, int32_t* tile, int32_t* zchunk);
 
-/* Choose the launch shape: looks up the device and the members' shapes in cache_path (JSON
- * lines; NULL = no cache) and otherwise times `reps` trial stages of every feasible (tile, z chunk)
- * and appends the fastest to the cache.  A trial rewrites only buffers that are dead between steps
- * (the second state buffer and the RK register) and discards its conserved totals, so the
- * members' states are unchanged.  *best_ms (may be NULL) receives the stage time.  Synchronises.
- * Errors: AT_E_STATE (empty batch), AT_E_SCHEDULE, AT_E_INVAL, AT_E_HIP. */
+/* Choose the launch shape: looks up the device, the members' shapes and the fraction f of their
+ * remaining scheduled steps that read delayed levels in cache_path (JSON lines; NULL = no cache);
+ * otherwise times, for every feasible (tile, z chunk), `reps` synchronous trial stages and `reps`
+ * delayed ones (each member at the delays of its first delayed step), keeps the shape with the
+ * least (1 - f) t_sync + f t_delayed and appends it to the cache.  A trial rewrites only buffers
+ * that are dead between steps (the second state buffer and the RK register) and discards its
+ * conserved totals, so the members' states are unchanged.  *best_ms (may be NULL) receives the
+ * weighted stage time.  Synchronises.  Errors: AT_E_STATE (empty batch), AT_E_SCHEDULE,
+ * AT_E_INVAL, AT_E_HIP. */
 ATNS_API int at_batch_autotune(at_batch* batch, const char* cache_path, int32_t reps, double* best_ms);
 
 /* Graph capture on (default) or off (launches enqueued directly); graph capture and replay counts. */

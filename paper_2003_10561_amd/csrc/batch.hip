@@ -84,7 +84,7 @@ struct ChunkPlan {
   int64_t nsw = 0, nvw = 0;  // stage / view work-list entries
   bool views = false;        // launch the batched AT sums at every stage
   std::vector<int> forced;   // indices of forced runs
-  std::vector<uint8_t> at;   // per step of the chunk: does some member read a delayed level
+
   size_t off_sw = 0, off_vw = 0, off_fh = 0, off_args = 0, total = 0, argb = 0;
 };
 
@@ -101,10 +101,7 @@ ChunkPlan plan_chunk(const at_batch* b, int K) {
     }
     if (s->cfg.forcing) p.forced.push_back((int)m);
   }
-  p.at.assign((size_t)K, 0);
-  for (const at_sim* s : b->runs)
-    for (int bs = 0; bs < K; ++bs)
-      if ((size_t)(s->step + bs) < s->step_delayed.size() && s->step_delayed[(size_t)(s->step + bs)]) p.at[(size_t)bs] = 1;
+
   size_t off = 0;
   p.off_sw = off;
   off = align_up(off + (size_t)p.nsw * sizeof(uint2));
@@ -230,10 +227,12 @@ hipError_t enqueue_chunk(at_batch* b, const ChunkPlan& p, hipStream_t st) {
         if (e != hipSuccess) return e;
       }
       // runs that read delayed levels at this step run the AT instantiation, the others the
-      // plain one (each leaves the other's launch at once)
+      // plain one (each leaves the other's launch at once); both are launched at every stage of a
+      // batch with any delayed schedule, so that a chunk's graph depends only on membership,
+      // launch shape and length
       hipError_t e = launch_fused_batch<T>(tab, sw, p.nsw, b->tile, forced, stg == 0, false, kModeStepH, st);
       if (e != hipSuccess) return e;
-      if (p.at[(size_t)bs]) {
+      if (p.views) {
         e = launch_fused_batch<T>(tab, sw, p.nsw, b->tile, forced, stg == 0, true, kModeStepH, st);
         if (e != hipSuccess) return e;
       }
@@ -250,7 +249,6 @@ std::vector<uint64_t> chunk_signature(const at_batch* b, const ChunkPlan& p) {
     sg.push_back((uint64_t)(uintptr_t)s);
     sg.push_back((uint64_t)s->cfg.forcing);
   }
-  for (uint8_t f : p.at) sg.push_back(f);
   return sg;
 }
 
@@ -294,11 +292,20 @@ int do_batch_steps(at_batch* b, int K) {
   return AT_OK;
 }
 
-// One trial stage (stage 1 of the current step, no publication, FP64 totals discarded) of every
-// run with the given launch shape.  It rewrites only buffers that hold no live data between
-// steps: the other state buffer and the RK register.
+// First step at or after the run's current step that reads delayed levels, or -1.
+int64_t first_delayed_step(const at_sim* s) {
+  for (size_t n = (size_t)s->step; n < s->step_delayed.size(); ++n)
+    if (s->step_delayed[n]) return (int64_t)n;
+  return -1;
+}
+
+// One trial stage (stage 1, no publication, FP64 totals discarded) of every run with the given
+// launch shape: synchronous (every run in the plain instantiation), or delayed (every run that
+// ever reads delayed levels takes the delays of its first such step and the AT instantiation).
+// It rewrites only buffers that hold no live data between steps: the other state buffer and the
+// RK register.
 template <typename T>
-int trial_stage(at_batch* b, int tile, int zchunk, int reps, double* ms) {
+int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, double* ms) {
   const int t0 = b->tile, z0 = b->zchunk;
   b->tile = tile;
   b->zchunk = zchunk;
@@ -313,6 +320,7 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, double* ms) {
   uint2* sw = (uint2*)(h + p.off_sw);
   int64_t is = 0;
   size_t tot_off = 0;
+  bool any_at = false;
   const size_t M = b->runs.size();
   for (size_t m = 0; m < M; ++m) {
     at_sim* s = b->runs[m];
@@ -323,14 +331,21 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, double* ms) {
     a.publish = 0;
     if (s->cfg.forcing) a.force.table = (T*)(s->ws + s->L.force_table);
     tot_off += (size_t)s->L.ntot * kNQ;
-    const int views = s->step_delayed[(size_t)s->step] ? 1 : 0;
+    int views = 0;
+    const int64_t nd = delayed ? first_delayed_step(s) : -1;
+    if (nd >= 0) {
+      a.delays = s->d_sched + (size_t)nd * s->g.ntiles * 6;
+      a.step_mod_r = (int)(nd % s->g.R);
+      views = 1;
+      any_at = true;
+    }
     pack_batch_arg<T>(a, tile, zc, views, h + p.off_args + m * p.argb);
   }
   HIP_TRY(upload(b, slot, p.total));
   const bool forced = !p.forced.empty();
   const void* tab = b->d_buf + p.off_args;
   const uint2* dsw = (const uint2*)(b->d_buf + p.off_sw);
-  const bool at = p.at[0] != 0;
+  const bool at = any_at;
   auto trial = [&]() -> hipError_t {
     hipError_t e = launch_fused_batch<T>(tab, dsw, p.nsw, tile, forced, false, false, kModeStepH, b->stream);
     if (e == hipSuccess && at) e = launch_fused_batch<T>(tab, dsw, p.nsw, tile, forced, false, true, kModeStepH, b->stream);
@@ -415,9 +430,25 @@ void cache_store(const char* path, const std::string& key, int tile, int zchunk,
   f << "{\"key\": \"" << key << buf;
 }
 
+// Fraction of the members' remaining scheduled steps that read delayed levels.
+double delayed_fraction(const at_batch* b) {
+  double tot = 0.0, del = 0.0;
+  for (const at_sim* s : b->runs)
+    for (size_t n = (size_t)s->step; n < s->step_delayed.size(); ++n) {
+      tot += 1.0;
+      del += s->step_delayed[n] ? 1.0 : 0.0;
+    }
+  return tot > 0.0 ? del / tot : 0.0;
+}
+
+// Launch shape from timed trial stages: for every feasible (tile, z chunk) the synchronous and
+// the delayed trial, weighted by the fraction of remaining steps that read delayed levels.
 template <typename T>
 int do_autotune(at_batch* b, const char* cache, int reps, double* best_ms) {
-  const std::string key = tune_key(b);
+  const double f = delayed_fraction(b);
+  char fbuf[32];
+  std::snprintf(fbuf, sizeof(fbuf), "|delayed=%.2f", f);
+  const std::string key = tune_key(b) + fbuf;
   int t = -1, z = -1;
   double ms = 0.0;
   if (cache_lookup(cache, key, &t, &z, &ms) && tile_fits(b, t)) {
@@ -445,9 +476,11 @@ int do_autotune(at_batch* b, const char* cache, int reps, double* best_ms) {
     if (!tile_fits(b, tile)) continue;
     for (int zc : kZ) {
       if (zc > maxz && zc != kZ[0]) break;
-      double m = 0.0;
-      int rc = trial_stage<T>(b, tile, zc, reps, &m);
+      double m_sync = 0.0, m_at = 0.0;
+      int rc = trial_stage<T>(b, tile, zc, reps, false, &m_sync);
+      if (!rc && f > 0.0) rc = trial_stage<T>(b, tile, zc, reps, true, &m_at);
       if (rc) return rc;
+      const double m = (1.0 - f) * m_sync + f * m_at;
       if (m < best) {
         best = m;
         bt = tile;

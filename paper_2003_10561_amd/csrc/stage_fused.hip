@@ -883,6 +883,14 @@ FArgs<T> pack(const StageArgs<T>& s, int zchunk) {
   return a;
 }
 
+// Occupancy target of the AT instantiations: their extra state does not fit the registers of 4
+// waves per SIMD without spilling, so workgroups of at most 8 waves (which run at 2 waves per
+// SIMD) target 2; larger workgroups keep the target they need to be resident at all.
+template <int BX, int BY>
+constexpr int at_waves(int minw) {
+  return Tile<BX, BY>::NT <= 512 ? (minw < 2 ? minw : 2) : minw;
+}
+
 // Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950).
 template <typename T, int BX, int BY>
 constexpr size_t stage_static_lds() {
@@ -907,12 +915,13 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
     a.gby = (int)gy;
     const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid(gx * gy * gz), block(Tile<BX, BY>::NT);
+    constexpr int MA = at_waves<BX, BY>(MINW);
     if (s.publish && at)
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, true>), grid, block, dyn, stream, a, mode);
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MA, true, true>), grid, block, dyn, stream, a, mode);
     else if (s.publish)
       hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, false>), grid, block, dyn, stream, a, mode);
     else if (at)
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, true>), grid, block, dyn, stream, a, mode);
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MA, false, true>), grid, block, dyn, stream, a, mode);
     else
       hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, false>), grid, block, dyn, stream, a, mode);
     return hipGetLastError();
@@ -1100,12 +1109,13 @@ hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, b
     const size_t dyn = forced ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid((unsigned)nblk), block(Tile<BX, BY>::NT);
     const FArgs<T>* r = (const FArgs<T>*)runs;
+    constexpr int MA = at_waves<BX, BY>(MINW);
     if (publish && at)
-      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, true>), grid, block, dyn, stream, r, work, mode);
+      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MA, true, true>), grid, block, dyn, stream, r, work, mode);
     else if (publish)
       hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, false>), grid, block, dyn, stream, r, work, mode);
     else if (at)
-      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, true>), grid, block, dyn, stream, r, work, mode);
+      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MA, false, true>), grid, block, dyn, stream, r, work, mode);
     else
       hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, false>), grid, block, dyn, stream, r, work, mode);
     return hipGetLastError();
