@@ -219,7 +219,7 @@ def batched_workload(torch, atns, W, steps, warmup, cache):
                         "launch per kernel per RK stage from a HIP graph"}
 
 
-def served_workload(atns, W, seconds, seed=5):
+def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64):
     """Poisson arrivals at 20/s for `seconds`; N = 32 round(exp(U(ln 32, ln 256)) / 32); steps ~ U{20..200};
     delays as in the batched workload; request j seeded with 5000 + j.  Initial fields come from a pool of
     two seeded fields per size (building one per request on the host would dominate the latency)."""
@@ -242,7 +242,8 @@ def served_workload(atns, W, seconds, seed=5):
         L = int(rng.integers(1, 4))
         reqs.append(dict(arrival_s=t, n=n, p=2 if n == 32 else n // 32, steps=int(rng.integers(20, 201)),
                          mode=mode, L=L, seed=5000 + j, dt=dt, mu_ref=W.default_mu(n), q0=q))
-    res, makespan = atns.serve(reqs, precision="fp32", max_active=64, hbm_budget_bytes=200e9)
+    res, makespan = atns.serve(reqs, precision="fp32", max_active=64, hbm_budget_bytes=200e9, tile=tile,
+                               zchunk=zchunk)
     ok = [o for o in res if o["status"] == 0]
     lat = np.array([o["done_s"] - r["arrival_s"] for r, o in zip(reqs, res) if o["status"] == 0])
     work = sum(r["n"] ** 3 * r["steps"] for r, o in zip(reqs, res) if o["status"] == 0)
@@ -251,6 +252,7 @@ def served_workload(atns, W, seconds, seed=5):
             "p99_latency_s": float(np.percentile(lat, 99)), "throughput": work / makespan,
             "unit": "grid-pt-steps/s", "offered_load": offered, "makespan_s": makespan,
             "arrival_window_s": seconds, "nonfinite": int(sum(o["stats"]["nonfinite"] for o in ok)),
+            "tile": tile, "zchunk": zchunk,
             "workload": "Poisson 20/s, N log-uniform 32..256 (multiples of 32), 20..200 steps, CAA/SAA L 1..3, "
                         "FP32, continuous batching"}
 
@@ -346,7 +348,10 @@ def main():
         log(f"batched: {out['batched']}")
     if not args.no_serve:
         log("served trace ...")
-        out["served"] = served_workload(atns, W, args.serve_seconds)
+        # the launch shape the autotuner chose for the batched mix (same kind of runs), if measured
+        bt = out.get("batched", {})
+        out["served"] = served_workload(atns, W, args.serve_seconds, tile=bt.get("tile", -1),
+                                        zchunk=bt.get("zchunk", 64))
         log(f"served: {out['served']}")
     if not args.no_cpu:
         log("cpu oracle baseline ...")

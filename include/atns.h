@@ -242,7 +242,8 @@ ATNS_API int at_batch_destroy(at_batch* batch);
  * than max_active runs are active and its device footprint (workspace, staging, schedule) fits
  * both the HBM budget and the free device memory, joins the batch at the next step boundary,
  * and leaves at the boundary where it has done its steps, after its final statistics (and field,
- * if asked) are read back.  The server allocates and frees the workspaces itself.  Unforced cubes
+ * if asked) are read back.  The batch advances by the fewest steps any active run has left, at
+ * most 8, between admissions.  The server allocates and frees the workspaces itself.  Unforced cubes
  * only; each request's delays are AT_SYNC, AT_CAA (c_r = L + 1) or AT_SAA (seed).
  * ------------------------------------------------------------------------------------------- */
 typedef struct {

@@ -4,8 +4,11 @@
 // admitted runs join the batch at the next step boundary, every loop iteration advances all
 // members by one RK step (one launch per kernel per stage, replayed from a HIP graph while
 // membership is unchanged), and a run leaves at the boundary where it has done its steps, after
-// its final statistics (and optionally its field) are read back.  The server owns the workspaces
-// it allocates for admitted requests and frees them when they leave.
+// its final statistics (and optionally its field) are read back.  Each iteration advances the batch
+// by the fewest steps any active run has left, at most kMaxChunk (fewer host round trips; no run
+// overshoots, and admission waits at most that many steps).  The server owns the workspaces it
+// allocates for admitted requests and frees them when they leave.
+#include <algorithm>
 #include <chrono>
 #include <deque>
 #include <new>
@@ -20,6 +23,7 @@ using namespace atns;
 namespace {
 
 using Clock = std::chrono::steady_clock;
+constexpr int64_t kMaxChunk = 8;
 
 struct Active {
   int req;
@@ -183,7 +187,9 @@ extern "C" int at_serve(const at_serve_config* sc, const at_request* reqs, int32
       }
       continue;
     }
-    rc = at_batch_step(batch, 1);
+    int64_t chunk = kMaxChunk;
+    for (const Active& a : active) chunk = std::min(chunk, a.end_step - a.sim->step);
+    rc = at_batch_step(batch, (int32_t)std::max<int64_t>(chunk, 1));
     if (rc) break;
     for (size_t k = 0; k < active.size();) {
       Active& a = active[k];

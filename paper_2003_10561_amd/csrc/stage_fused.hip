@@ -507,7 +507,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       for (int c = 0; c < 5; ++c) fq[c] = qin[c * N + fi];
       if (mode == kModeStep && a.rk_a != T(0)) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) fd[c] = a.dq[c * N + fi];
+        for (int c = 0; c < 5; ++c) fd[c] = __builtin_nontemporal_load(a.dq + c * N + fi);
       }
     }
 
@@ -713,13 +713,15 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       }
       if (mode == kModeRhs) {
 #pragma unroll
-        for (int c = 0; c < kNQ; ++c) a.rhs_out[c * N + fi] = r[c];
+        for (int c = 0; c < kNQ; ++c) __builtin_nontemporal_store(r[c], a.rhs_out + c * N + fi);
       } else {
 #pragma unroll
         for (int c = 0; c < kNQ; ++c) {
           const T d = (a.rk_a == T(0)) ? a.dt * r[c] : a.rk_a * fd[c] + a.dt * r[c];
-          if (a.store_dq) a.dq[c * N + fi] = d;
-          a.q_out[c * N + fi] = fq[c] + a.rk_b * d;
+          // the register and the new state are not read again in this stage: streaming stores
+          // keep the L2 for the halo planes
+          if (a.store_dq) __builtin_nontemporal_store(d, a.dq + c * N + fi);
+          __builtin_nontemporal_store(fq[c] + a.rk_b * d, a.q_out + c * N + fi);
           s_tsum[c][tid] += (double)d;
         }
       }
@@ -935,57 +937,58 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
 // that face the value there is the extrapolation w_0 v^{n-k} + w_1 v^{n-k-1} + w_2 v^{n-k-2},
 // w from kappa = k + c_s (the Appendix B weights at c_s = 0); the kernel stores, for each of the 9
 // ring components, sum_m a_m (extrapolated value at X + m) at the reader's own ring offset, with
-// a = (1, -8, 8, -1) the stencil numerators.  Readers whose face has k = 0 are not written.
+// a = (1, -8, 8, -1) the stencil numerators.  One thread serves the two readers of a face (layers
+// 0, 1 or 2, 3), which share their delay and the source points across it (each extrapolated
+// once).  Readers whose face has k = 0 are not written.
 template <typename T>
 __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid) {
-  const uint32_t total = a.slab0 + a.slab1 + a.slab2;
-  if (tid >= total) return;
+  const uint32_t h0 = a.slab0 / 2, h1 = a.slab1 / 2, h2 = a.slab2 / 2;
+  if (tid >= h0 + h1 + h2) return;
   int d, x, y, z, jp;
-  uint32_t sidx, jstride;  // slab index of the reader, stride of the layer index jp in it
-  if (tid < a.slab0) {
+  uint32_t sidx, jstride;  // slab index of the pair's first reader, stride of the layer index jp
+  if (tid < h0) {
     d = 0;
-    sidx = tid;
-    const int q = 4 * a.px;
-    jp = (int)(sidx % q);
-    const uint32_t r = sidx / q;
+    const int q = 2 * a.px;  // reader pairs per (y, z) row
+    const int jpp = (int)(tid % q);
+    const uint32_t r = tid / q;
     y = (int)(r % a.ny);
     z = (int)(r / a.ny);
     x = 0;
+    jp = 2 * jpp;
     jstride = 1;
-  } else if (tid < a.slab0 + a.slab1) {
+    sidx = r * (uint32_t)(4 * a.px) + (uint32_t)jp;
+  } else if (tid < h0 + h1) {
     d = 1;
-    sidx = tid - a.slab0;
-    x = (int)(sidx % a.nx);
-    const uint32_t r = sidx / a.nx;
-    jp = (int)(r % (4 * a.py));
-    z = (int)(r / (4 * a.py));
+    const uint32_t u = tid - h0;
+    x = (int)(u % a.nx);
+    const uint32_t r = u / a.nx;
+    const int jpp = (int)(r % (2 * a.py));
+    z = (int)(r / (2 * a.py));
     y = 0;
+    jp = 2 * jpp;
     jstride = (uint32_t)a.nx;
+    sidx = ((uint32_t)z * (uint32_t)(4 * a.py) + (uint32_t)jp) * (uint32_t)a.nx + (uint32_t)x;
   } else {
     d = 2;
-    sidx = tid - a.slab0 - a.slab1;
-    x = (int)(sidx % a.nx);
-    const uint32_t r = sidx / a.nx;
+    const uint32_t u = tid - h0 - h1;
+    x = (int)(u % a.nx);
+    const uint32_t r = u / a.nx;
     y = (int)(r % a.ny);
-    jp = (int)(r / a.ny);
+    const int jpp = (int)(r / a.ny);
     z = 0;
+    jp = 2 * jpp;
     jstride = (uint32_t)a.nx * (uint32_t)a.ny;
+    sidx = ((uint32_t)jp * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x;
   }
-  const int t = jp / 4, layer = jp % 4;
-  // the reader's PE: t along d, from the point's coordinates across
+  const int t = jp / 4, lower = (jp % 4) == 0;  // readers on layers 0, 1 (lower face) or 2, 3
+  // the readers' PE: t along d, from the point's coordinates across
   const int rx = d == 0 ? t : x / a.ex, ry = d == 1 ? t : y / a.ey, rz = d == 2 ? t : z / a.ez;
-  const int face = 2 * d + (layer < 2 ? 0 : 1);
-  const int k = a.delays[((rz * a.py + ry) * a.px + rx) * 6 + face];
+  const int k = a.delays[((rz * a.py + ry) * a.px + rx) * 6 + 2 * d + (lower ? 0 : 1)];
   if (k <= 0) return;
   const int pd = d == 0 ? a.px : (d == 1 ? a.py : a.nz / a.ez);
-  const int tn = layer < 2 ? (t == 0 ? pd - 1 : t - 1) : (t == pd - 1 ? 0 : t + 1);
-  // crossing offsets of this layer: (source layer in PE tn, stencil numerator)
-  int ns = 0, sl0 = 0, sl1 = 0;
-  T a0 = T(0), a1 = T(0);
-  if (layer == 0) { ns = 2; sl0 = 2; a0 = T(1); sl1 = 3; a1 = T(-8); }
-  else if (layer == 1) { ns = 1; sl0 = 3; a0 = T(1); }
-  else if (layer == 2) { ns = 1; sl0 = 0; a0 = T(-1); }
-  else { ns = 2; sl0 = 0; a0 = T(8); sl1 = 1; a1 = T(-1); }
+  const int tn = lower ? (t == 0 ? pd - 1 : t - 1) : (t == pd - 1 ? 0 : t + 1);
+  // sources: lower face: layers 2, 3 of PE tn; upper face: layers 0, 1 of PE tn
+  const int sl = lower ? 2 : 0;
   const T kap = T(k) + a.cstage;
   const T w0 = (kap + T(1)) * (kap + T(2)) * T(0.5);
   const T w1 = -kap * (kap + T(2));
@@ -996,20 +999,23 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
   const int s2 = s1 == 0 ? a.R - 1 : s1 - 1;
   const uint32_t base = d == 0 ? 0u : (d == 1 ? a.rdir1 : a.rdir2);
   const uint32_t ss = d == 0 ? a.slab0 : (d == 1 ? a.slab1 : a.slab2);
-  const uint32_t src0 = base + sidx + (uint32_t)(4 * tn + sl0 - jp) * jstride;
-  const uint32_t src1 = base + sidx + (uint32_t)(4 * tn + sl1 - jp) * jstride;
+  const uint32_t srcA = base + sidx + (uint32_t)(4 * tn + sl - jp) * jstride;  // layer sl
+  const uint32_t srcB = srcA + jstride;                                        // layer sl + 1
+  const uint32_t dst = base + sidx;
   const T* r0 = a.ring + (uint32_t)s0 * a.rslot;
   const T* r1 = a.ring + (uint32_t)s1 * a.rslot;
   const T* r2 = a.ring + (uint32_t)s2 * a.rslot;
 #pragma unroll
   for (int c = 0; c < kNRing; ++c) {
-    const uint32_t o0 = src0 + (uint32_t)c * ss;
-    T v = a0 * (w0 * r0[o0] + w1 * r1[o0] + w2 * r2[o0]);
-    if (ns == 2) {
-      const uint32_t o1 = src1 + (uint32_t)c * ss;
-      v += a1 * (w0 * r0[o1] + w1 * r1[o1] + w2 * r2[o1]);
-    }
-    gv[base + sidx + (uint32_t)c * ss] = v;
+    const uint32_t oa = srcA + (uint32_t)c * ss, ob = srcB + (uint32_t)c * ss;
+    const T va = w0 * r0[oa] + w1 * r1[oa] + w2 * r2[oa];
+    const T vb = w0 * r0[ob] + w1 * r1[ob] + w2 * r2[ob];
+    // lower face: reader 0 = 1 va - 8 vb (offsets -2, -1), reader 1 = 1 vb (offset -2);
+    // upper face: reader 2 = -1 va (offset +2), reader 3 = 8 va - 1 vb (offsets +1, +2)
+    const T v0 = lower ? va - T(8) * vb : -va;
+    const T v1 = lower ? vb : T(8) * va - vb;
+    gv[dst + (uint32_t)c * ss] = v0;
+    gv[dst + jstride + (uint32_t)c * ss] = v1;
   }
 }
 
@@ -1034,7 +1040,7 @@ __global__ __launch_bounds__(256) void k_at_sums_batch(const FArgs<T>* __restric
 template <typename T>
 hipError_t launch_at_sums(const StageArgs<T>& a, hipStream_t stream) {
   const Geom& g = a.g;
-  const int64_t total = g.slab[0] + g.slab[1] + g.slab[2];
+  const int64_t total = (g.slab[0] + g.slab[1] + g.slab[2]) / 2;  // reader pairs
   hipLaunchKernelGGL(k_at_sums<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
                      pack<T>(a, 4), a.gv_out);
   return hipGetLastError();
@@ -1097,7 +1103,7 @@ void pack_batch_arg(const StageArgs<T>& s, int tile, int zchunk, int views, void
   std::memcpy(dst, &a, sizeof(a));
 }
 
-int64_t view_blocks(const Geom& g) { return (g.slab[0] + g.slab[1] + g.slab[2] + 255) / 256; }
+int64_t view_blocks(const Geom& g) { return (g.slab[0] + g.slab[1] + g.slab[2]) / 2 / 256 + 1; }
 
 namespace {
 template <typename T, int BX, int BY, int MINW>
