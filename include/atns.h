@@ -162,10 +162,10 @@ ATNS_API int at_field_device(at_sim* sim, void** dev_ptr);
 
 /* Launch shape of the fused stage kernel: `tile` (0 .. AT_N_TILES-1) selects the workgroup column
  * tile and register budget (0: 64x8, 1: 32x8, 2: 32x8 at higher occupancy, 3: 32x4, 4: 64x4,
- * 5: 16x8 points in x-y), `zchunk` (>= 4) the number of z planes each workgroup marches through.
+ * 5: 16x8, 6: 16x16 points in x-y), `zchunk` (>= 4) the number of z planes each workgroup marches through.
  * Results do not depend on either (every point is computed by the same arithmetic); only speed
  * does.  Set by the autotuner.  Errors: AT_E_INVAL. */
-#define AT_N_TILES 6
+#define AT_N_TILES 7
 ATNS_API int at_set_tuning(at_sim* sim, int32_t tile, int32_t zchunk);
 ATNS_API int at_get_tuning(at_sim* sim, int32_t* tile, int32_t* zchunk);
 

@@ -26,7 +26,7 @@ EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "a
             "at_batch_create", "at_batch_add", "at_batch_remove", "at_batch_size", "at_batch_step",
             "at_batch_set_tuning", "at_batch_get_tuning", "at_batch_autotune", "at_batch_set_graph",
             "at_batch_graph_stats", "at_batch_destroy", "at_serve"]
-N_TILES = 6
+N_TILES = 7
 N_KERNELS = 6
 
 

@@ -84,14 +84,15 @@ struct StageArgs {
 struct TileShape {
   int bx, by, waves;
 };
-constexpr int kTileCount = 6;
+constexpr int kTileCount = 7;
 __host__ __device__ constexpr TileShape tile_shape(int t) {
   return t == 0 ? TileShape{64, 8, 4}
        : t == 1 ? TileShape{32, 8, 2}
        : t == 2 ? TileShape{32, 8, 4}
        : t == 3 ? TileShape{32, 4, 2}
        : t == 4 ? TileShape{64, 4, 3}
-                : TileShape{16, 8, 2};
+       : t == 5 ? TileShape{16, 8, 2}
+                : TileShape{16, 16, 4};
 }
 __host__ __device__ inline int tile_bx(int t) { return tile_shape(t).bx; }
 __host__ __device__ inline int tile_by(int t) { return tile_shape(t).by; }

@@ -1067,6 +1067,7 @@ size_t fused_lds_bytes(int tile, size_t word, bool forced) {
     case 3: return stage_lds_bytes<32, 4>(word, forced);
     case 4: return stage_lds_bytes<64, 4>(word, forced);
     case 5: return stage_lds_bytes<16, 8>(word, forced);
+    case 6: return stage_lds_bytes<16, 16>(word, forced);
     default: return ~size_t(0);
   }
 }
@@ -1082,6 +1083,7 @@ hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, b
     case 3: return launch_cfg<T, 32, 4, f32 ? 2 : 1>(a, zchunk, mode, at, stream);
     case 4: return launch_cfg<T, 64, 4, f32 ? 3 : 2>(a, zchunk, mode, at, stream);
     case 5: return launch_cfg<T, 16, 8, f32 ? 2 : 1>(a, zchunk, mode, at, stream);
+    case 6: return launch_cfg<T, 16, 16, f32 ? 4 : 2>(a, zchunk, mode, at, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1142,6 +1144,7 @@ hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk,
     case 3: return launch_batch_cfg<T, 32, 4, f32 ? 2 : 1>(runs, work, nblk, forced, publish, at, mode, stream);
     case 4: return launch_batch_cfg<T, 64, 4, f32 ? 3 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
     case 5: return launch_batch_cfg<T, 16, 8, f32 ? 2 : 1>(runs, work, nblk, forced, publish, at, mode, stream);
+    case 6: return launch_batch_cfg<T, 16, 16, f32 ? 4 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -112,3 +112,12 @@ def test_batch_and_serve_argument_checks_without_gpu(lib):
     assert lib.at_serve(C.byref(sc), reqs, 2, None, res, None) == atns.AT_E_INVAL
     bad = atns._ServeConfig(atns.FP32, 0, -1, 64, 1e9)
     assert lib.at_serve(C.byref(bad), reqs, 0, None, res, None) == atns.AT_E_INVAL
+
+
+def test_grid_beyond_32bit_offsets_rejected(lib):
+    """The largest grids: element offsets of one handle must stay below 2^32."""
+    ok = cfg(n=(1024, 1024, 512), p=(16, 16, 8), max_delay=1)  # ring: 4 x 9 x 100M < 2^32
+    assert lib.at_workspace_bytes(C.byref(ok.to_c())) > 0
+    big = cfg(n=(2048, 2048, 512), p=(32, 32, 8))  # 5 * N >= 2^32
+    assert lib.at_workspace_bytes(C.byref(big.to_c())) == 0
+    assert "2^32" in lib.at_last_error().decode()

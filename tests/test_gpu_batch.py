@@ -236,3 +236,19 @@ def test_batch_error_paths():
     b.remove(s)
     assert len(b) == 0
     s.rk_step(1)  # still usable alone
+
+
+def test_empty_and_zero_step_edge_cases():
+    """Zero steps change nothing; an empty batch steps and tunes as a no-op / clear error."""
+    s = make_run(0, RUNS[0], "fp32")[0]
+    f0 = s.get_field()
+    s.rk_step(0)
+    assert np.array_equal(s.get_field(), f0) and s.stats()["step"] == 0
+    b = atns.Batch("fp32")
+    b.step(3)  # no members: nothing to do
+    with pytest.raises(atns.AtError) as e:
+        b.autotune(None, reps=1)
+    assert e.value.rc == atns.AT_E_STATE
+    b.add(s)
+    b.step(0)
+    assert np.array_equal(s.get_field(), f0)

@@ -87,3 +87,8 @@ def test_admission_limits():
     res, _ = atns.serve(reqs, max_active=2, hbm_budget_bytes=budget)
     assert res[2]["status"] == atns.AT_E_WORKSPACE
     assert all(o["status"] == 0 for j, o in enumerate(res) if j != 2)
+
+
+def test_empty_trace():
+    res, makespan = atns.serve([], max_active=4)
+    assert res == [] and makespan >= 0.0
