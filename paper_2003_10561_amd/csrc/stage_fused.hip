@@ -449,17 +449,19 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   auto plane_delays = [&](int zpl) {
     if (!AT) return;
     const int gzp = pmod(zpl, nz), tzp = gzp / a.ez;
-    if (column && tzp != tz_c) {
+    if (tzp != tz_c) {  // uniform: a new z-PE
       tz_c = tzp;
-      const int8_t* kf = a.delays + ((tzp * a.py + ty) * a.px + tx) * 6;
-      kcx = near_x ? (lxe < 2 ? kf[0] : kf[1]) : 0;
-      kcy = near_y ? (lye < 2 ? kf[2] : kf[3]) : 0;
-      kzl = kf[4];
-      kzh = kf[5];
+      if (column) {
+        const int8_t* kf = a.delays + ((tzp * a.py + ty) * a.px + tx) * 6;
+        kcx = near_x ? (lxe < 2 ? kf[0] : kf[1]) : 0;
+        kcy = near_y ? (lye < 2 ? kf[2] : kf[3]) : 0;
+        kzl = kf[4];
+        kzh = kf[5];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
-        bx[mi] = (kcx > 0 && ((cxm >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
-        by[mi] = (kcy > 0 && ((cym >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
+        for (int mi = 0; mi < 4; ++mi) {
+          bx[mi] = (kcx > 0 && ((cxm >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
+          by[mi] = (kcy > 0 && ((cym >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
+        }
       }
     }
     if (__builtin_expect(kcx > 0, 0)) {
@@ -523,6 +525,9 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       // crosses a delayed face the points across carry coefficient 0 and the reader's AT sum
       // replaces them; elsewhere the central form is the same expression in every instantiation
       // (so a run's result does not depend on whether another run of its batch is delayed)
+      // the masked forms only in waves that hold a reader of a delayed face (wave-uniform test)
+      const bool wx = AT && __builtin_amdgcn_ballot_w64(kcx > 0) != 0;
+      const bool wy = AT && __builtin_amdgcn_ballot_w64(kcy > 0) != 0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const T xm2 = s_pr[bc][c][py][px - 2], xm1 = s_pr[bc][c][py][px - 1], xp1 = s_pr[bc][c][py][px + 1],
@@ -531,8 +536,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
                 yp2 = s_pr[bc][c][py + 2][px];
         T dx = xm2 - T(8) * xm1 + T(8) * xp1 - xp2;
         T dy = ym2 - T(8) * ym1 + T(8) * yp1 - yp2;
-        if (__builtin_expect(kcx > 0, 0)) dx = bx[0] * xm2 + bx[1] * xm1 + bx[2] * xp1 + bx[3] * xp2 + vx[c];
-        if (__builtin_expect(kcy > 0, 0)) dy = by[0] * ym2 + by[1] * ym1 + by[2] * yp1 + by[3] * yp2 + vy[c];
+        if (wx && kcx > 0) dx = bx[0] * xm2 + bx[1] * xm1 + bx[2] * xp1 + bx[3] * xp2 + vx[c];
+        if (wy && kcy > 0) dy = by[0] * ym2 + by[1] * ym1 + by[2] * yp1 + by[3] * yp2 + vy[c];
         set_grad(G, c, 0, dx * a.i12x);
         set_grad(G, c, 1, dy * a.i12y);
         set_grad(G, c, 2, (WIN(c, 0) - T(8) * WIN(c, 1) + T(8) * WIN(c, 3) - WIN(c, 4)) * a.i12z);
@@ -637,6 +642,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
           // offset m = -r from receiver zc + r; a receiver in another z-PE whose face is delayed
           // takes no contribution from it and adds its AT sum instead when it is finalized (the
           // receiver's PE owns that decision).
+          // only a source within 2 planes of its z-PE's faces (uniform) has receivers across
+          const bool zface = AT && (lze < 2 || lze >= a.ez - 2);
 #pragma unroll
           for (int ri = 0; ri < 4; ++ri) {
             const int r = ri < 2 ? ri - 2 : ri - 1;
@@ -644,12 +651,16 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
             if (zp < z0 || zp >= z1) continue;
             const int m = -r;
             const T cm = ((m == -2) ? T(1) : (m == -1) ? T(-8) : (m == 1) ? T(8) : T(-1)) * a.i12z;
-            const int gzp = pmod(zp, nz);
-            const int tzp = gzp / a.ez;
-            const int l = gzp - tzp * a.ez + m;
-            int k = 0;
-            if (AT && (l < 0 || l >= a.ez)) k = a.delays[((tzp * a.py + ty) * a.px + tx) * 6 + (l < 0 ? 4 : 5)];
-            if (k == 0) {
+            bool keep = true;
+            if (zface) {
+              const int l = lze - m;  // the receiver in this z-PE's local coordinates
+              if (l < 0 || l >= a.ez) {
+                const int gzp = pmod(zp, nz);
+                const int tzp = gzp / a.ez;
+                keep = a.delays[((tzp * a.py + ty) * a.px + tx) * 6 + (l < 0 ? 5 : 4)] == 0;
+              }
+            }
+            if (keep) {
 #pragma unroll
               for (int c = 0; c < kNQ; ++c) acc[2 + r][c] -= cm * F[c];
             }
@@ -660,6 +671,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
 
     if (valid && zin_d && mode != kModePublish) {
       const int fxx = px - 2, fyy = py - 2;  // this point in s_fx (column) and s_fy (row)
+      const bool wx = AT && __builtin_amdgcn_ballot_w64(kcx_d > 0) != 0;
+      const bool wy = AT && __builtin_amdgcn_ballot_w64(kcy_d > 0) != 0;
 #pragma unroll
       for (int c = 0; c < kNQ; ++c) {
         const T xm2 = s_fx[bd][c][py - 4][fxx - 2], xm1 = s_fx[bd][c][py - 4][fxx - 1],
@@ -668,8 +681,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
                 yp1 = s_fy[bd][c][fyy + 1][px - 4], yp2 = s_fy[bd][c][fyy + 2][px - 4];
         T dfx = xm2 - T(8) * xm1 + T(8) * xp1 - xp2;
         T dfy = ym2 - T(8) * ym1 + T(8) * yp1 - yp2;
-        if (__builtin_expect(kcx_d > 0, 0)) dfx = bxd[0] * xm2 + bxd[1] * xm1 + bxd[2] * xp1 + bxd[3] * xp2 + vfx[c];
-        if (__builtin_expect(kcy_d > 0, 0)) dfy = byd[0] * ym2 + byd[1] * ym1 + byd[2] * yp1 + byd[3] * yp2 + vfy[c];
+        if (wx && kcx_d > 0) dfx = bxd[0] * xm2 + bxd[1] * xm1 + bxd[2] * xp1 + bxd[3] * xp2 + vfx[c];
+        if (wy && kcy_d > 0) dfy = byd[0] * ym2 + byd[1] * ym1 + byd[2] * yp1 + byd[3] * yp2 + vfy[c];
         acc[1][c] -= dfx * a.i12x + dfy * a.i12y;
       }
     }
