@@ -88,16 +88,23 @@ def main():
     st_ms = sum(d for k, d in win if STAGE in k)
     gv_ms = sum(d for k, d in win if VIEWS in k)
     n_gv = sum(1 for k, _ in win if VIEWS in k)
-    per_kernel = {}
-    for k, d in seq:
-        c, t = per_kernel.get(k, (0, 0.0))
-        per_kernel[k] = (c + 1, t + d)
+    def table(entries, top):
+        per_kernel = {}
+        for k, d in entries:
+            c, t = per_kernel.get(k, (0, 0.0))
+            per_kernel[k] = (c + 1, t + d)
+        rows = ["| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
+        for k, (c, t) in sorted(per_kernel.items(), key=lambda kv: -kv[1][1])[:top]:
+            rows.append(f"| `{short_name(k)[:80]}` | {c} | {t / c:.3f} | {t:.1f} |")
+        return rows
+
     lines = [f"# Kernel trace: stage kernels, {a.workload}", "",
-             "Command (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "Command (R = the repository root; run from /tmp with `export TMPDIR=/tmp`):", "",
              "```", a.command.split(" ;; ")[0], "```", "",
-             "| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
-    for k, (c, t) in sorted(per_kernel.items(), key=lambda kv: -kv[1][1])[:12]:
-        lines.append(f"| `{short_name(k)[:80]}` | {c} | {t / c:.3f} | {t:.1f} |")
+             f"Kernels of the timed window (the last {a.timed} stage launches of the single-run workload):", ""]
+    lines += table(win, 12)
+    lines += ["", "Whole run, the 12 kernels with the most time (other workloads of the command included):", ""]
+    lines += table(seq, 12)
     lines += ["", f"Timed window (last {a.timed} stage launches):", "",
               f"- k_stage_avg_ms: {st_ms / a.timed:.4f}",
               f"- k_at_sums_launches: {n_gv}",
@@ -117,7 +124,7 @@ def main():
     sw = [v * 1024.0 * fw for k, v in write if STAGE in k]
     cmds = a.command.split(" ;; ")
     lines = [f"# HBM traffic: stage kernels, {a.workload}", "",
-             "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "", "```"]
+             "Commands (R = the repository root; run from /tmp with `export TMPDIR=/tmp`):", "", "```"]
     lines += cmds[1:] if len(cmds) > 1 else cmds
     lines += ["```", "",
               f"Copy calibration: for a device copy of {a.copy_bytes:.0f} bytes each way, bytes moved / "
