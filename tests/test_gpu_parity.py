@@ -127,6 +127,46 @@ def test_rhs_random_delays_history_levels(n, p):
     compare_fields(g.rhs().cpu().numpy(), o.rhs(), 1e-12, "rhs at next step")
 
 
+def test_tile_shapes_agree_on_wide_pes():
+    """PEs of 48 x 24 x 16: the 16x8 tile has workgroups whose columns and halos all lie inside one
+    PE along x and y (no x/y stencil of theirs crosses a face) next to workgroups at the faces; a
+    32-wide tile (32x4 in FP64, 32x8 in FP32) has none of the former.  FP64 parity with the oracle
+    over CAA steps with the 16x8 tile, and bitwise the same fields with the 32-wide tile."""
+    n, p = (96, 48, 32), (2, 2, 2)
+
+    def interior(x0, b, nn, e):  # every column of the tile and its halo 2 points inside one PE
+        l = (x0 - 2) % nn % e
+        return x0 + b <= nn and l >= 2 and l + b + 3 <= e - 3
+
+    assert any(interior(x, 16, 96, 48) for x in range(0, 96, 16))
+    assert any(interior(y, 8, 48, 24) for y in range(0, 48, 8))
+    assert not any(interior(x, 32, 96, 48) for x in range(0, 96, 32))
+    say("case wide PEs 96x48x32 on 2x2x2 PEs, CAA L=3, tile 16x8 vs 32-wide")
+    q = history_levels(n, 1, 77)[0]
+    g, o = pair(n, p, q)
+    schedule(g, o, atns.CAA, L=3, c_r=4, n_steps=10)
+    g.set_tuning(5, 32)
+    others = {}
+    for prec in ("fp64", "fp32"):
+        for tile in ((5, 32), (1, 32)) if prec == "fp32" else ((3, 32),):
+            h = atns.Sim(atns.Config(n=n, p=p, dt=W.default_dt(q), mu_ref=W.default_mu(n[0]), max_delay=3,
+                                     precision=prec))
+            h.init_field(q)
+            h.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=10)
+            h.set_tuning(*tile)
+            others[(prec, tile[0])] = h
+    for _ in range(8):
+        g.rk_step(1)
+        o.rk_step(1)
+        for h in others.values():
+            h.rk_step(1)
+        compare_stats(g.stats(), o.stats(), TOL64)
+    f = g.get_field()
+    compare_fields(f, o.field(), TOL64, "after 8 steps")
+    assert np.array_equal(f, others[("fp64", 3)].get_field())
+    assert np.array_equal(others[("fp32", 5)].get_field(), others[("fp32", 1)].get_field())
+
+
 def test_saa_seeded_schedule_matches_oracle_generator():
     """Random delays drawn by the library's SplitMix64 and the oracle's own implementation."""
     n, p = (32, 32, 32), (4, 4, 4)
