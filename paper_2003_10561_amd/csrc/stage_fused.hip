@@ -118,6 +118,25 @@ __device__ __forceinline__ int crossing_mask(int l, int e) {
   return (l == 0 ? 0x3 : l == 1 ? 0x1 : 0) | (l == e - 1 ? 0xC : l == e - 2 ? 0x8 : 0);
 }
 
+// Zero, produced by an instruction that reads v.  Added to the address of a fetch that refills the
+// registers whose old contents v was computed from, it keeps the fetch behind that computation:
+// issued earlier, the fetch would need other registers, and the copy back at the end of the
+// iteration would make the wave wait for it there.
+template <typename T>
+__device__ __forceinline__ uint32_t zero_after(T v) {
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z) : "v"(v));
+  return z;
+}
+
+// v in a register of its own (FP32): the window keeps rho and E of a plane, and as copies of the
+// state registers they would hold those until the end of the iteration, past the refill.
+__device__ __forceinline__ float own_copy(float v) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
+  return r;
+}
+
 // Primitives from conserved values: rho, u, v, w, T.
 template <typename T>
 __device__ __forceinline__ void prim_of(const T q[5], T inv_cv, T& r, T& u, T& v, T& w, T& t) {
@@ -312,6 +331,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     ex_ = e;
   }
   const int epx = exX - x0 + 4, epy = exY - y0 + 4;
+  const bool xwave = (tid >> 6) < (TL::NXTRA + 63) / 64;  // uniform across the wave
   const uint32_t xcol = (uint32_t)pmod(exY, ny) * nx + pmod(exX, nx);
 
   const int tx = gx / a.ex, ty = gy / a.ey;
@@ -498,7 +518,6 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     }
     const bool zin = zc >= z0 && zc < z1;
     const bool zin_d = zc - 1 >= z0 && zc - 1 < z1;
-    const int gzd = pmod(zc - 1, nz);
     // plane zc - 2 is finalized in this iteration: fetch its state and register now
     const int zf = zc - 2;
     const bool fin = valid && zf >= z0 && zf < z1 && mode != kModePublish;
@@ -739,6 +758,10 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         }
       }
     }
+    // the fetched state and register are consumed here on every path (no instruction: the wait
+    // for them happens now, not at the next write of their registers, after later fetches)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) asm volatile("" ::"v"(fq[c]), "v"(fd[c]));
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -757,33 +780,43 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         bxd[mi] = bx[mi];
         byd[mi] = by[mi];
       }
+      // consume what the last iteration fetched (the plane-only points of zc + 1, the column's
+      // plane zc + 3), then fetch ahead: every lane fetches, at a valid address, the plane after
+      // (zc + 2, zc + 4, wrapped), so that the wait counts on the fetches are exact
       plane_delays(zc + 1);
-      if (column) {
-        T r_, u_, v_, w_, t_;
-        prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
-        zw.push(u_, v_, w_, t_, r_, raw[4]);
-        if (zc + 4 <= z1 + 3) {
-          const uint32_t i = (uint32_t)pmod(zc + 4, nz) * plane + col;
+      T xt = T(0), t_ = T(0);
+      if (ex_ >= 0) {
+        T xr, xu, xv, xw;
+        prim_of<T>(xraw, inv_cv, xr, xu, xv, xw, xt);
+        s_pr[bn][0][epy][epx] = xu;
+        s_pr[bn][1][epy][epx] = xv;
+        s_pr[bn][2][epy][epx] = xw;
+        s_pr[bn][3][epy][epx] = xt;
+      }
 #pragma unroll
-          for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
+      for (int c = 0; c < 5; ++c) asm volatile("" ::"v"(xraw[c]));  // consumed on every path
+      if (column) {
+        T r_, u_, v_, w_, e_ = raw[4];
+        prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
+        if constexpr (kRegWin) {
+          r_ = own_copy(r_);
+          e_ = own_copy(e_);
         }
+        zw.push(u_, v_, w_, t_, r_, e_);
         s_pr[bn][0][py][px] = zw.get(0, 2);
         s_pr[bn][1][py][px] = zw.get(1, 2);
         s_pr[bn][2][py][px] = zw.get(2, 2);
         s_pr[bn][3][py][px] = zw.get(3, 2);
       }
-      if (ex_ >= 0) {
-        T xr, xu, xv, xw, xt;
-        prim_of<T>(xraw, inv_cv, xr, xu, xv, xw, xt);
-        if (zc + 2 <= z1 + 1) {
-          const uint32_t i = (uint32_t)pmod(zc + 2, nz) * plane + xcol;
+      {
+        const uint32_t i = (uint32_t)pmod(zc + 4, nz) * plane + col + zero_after(t_);
 #pragma unroll
-          for (int c = 0; c < 5; ++c) xraw[c] = qin[c * N + i];
-        }
-        s_pr[bn][0][epy][epx] = xu;
-        s_pr[bn][1][epy][epx] = xv;
-        s_pr[bn][2][epy][epx] = xw;
-        s_pr[bn][3][epy][epx] = xt;
+        for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
+      }
+      if (xwave || AT) {  // only the waves that hold plane-only points
+        const uint32_t i = (uint32_t)pmod(zc + 2, nz) * plane + xcol + zero_after(xt);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) xraw[c] = qin[c * N + i];
       }
     }
     __syncthreads();
