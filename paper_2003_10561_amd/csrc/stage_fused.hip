@@ -506,31 +506,13 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     T vfx[kNQ], vfy[kNQ];
 #pragma unroll
     for (int c = 0; c < kNQ; ++c) vfx[c] = vfy[c] = T(0);
-    if (__builtin_expect(valid && kcx_d > 0, 0)) {
-      const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsx + opx;
-#pragma unroll
-      for (int c = 0; c < kNQ; ++c) vfx[c] = at_sum<T>(a, 0, 4 + c, o);
-    }
-    if (__builtin_expect(valid && kcy_d > 0, 0)) {
-      const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsy + opy;
-#pragma unroll
-      for (int c = 0; c < kNQ; ++c) vfy[c] = at_sum<T>(a, 1, 4 + c, o);
-    }
     const bool zin = zc >= z0 && zc < z1;
     const bool zin_d = zc - 1 >= z0 && zc - 1 < z1;
-    // plane zc - 2 is finalized in this iteration: fetch its state and register now
+    // plane zc - 2 is finalized in this iteration
     const int zf = zc - 2;
     const bool fin = valid && zf >= z0 && zf < z1 && mode != kModePublish;
     const uint32_t fi = (uint32_t)pmod(zf, nz) * plane + col;
     T fq[5], fd[5];
-    if (fin) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) fq[c] = qin[c * N + fi];
-      if (mode == kModeStep && a.rk_a != T(0)) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) fd[c] = __builtin_nontemporal_load(a.dq + c * N + fi);
-      }
-    }
 
     // fluxes of this column at plane zc: the tile computes all three (F_z also just outside the
     // chunk, for the z divergence), the halo rows F_y and the halo columns F_x
@@ -576,6 +558,29 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
           set_grad(G, c, 2, dz * a.i12z);
         }
       }
+      // fetched now, after the gradients, so that the gradients' wait for their AT sums (fetched in
+      // the last iteration) covers no newer fetch; the fluxes hide these: the state and register of
+      // the plane finalized in this iteration and the divergence AT sums of plane zc - 1 (the lanes
+      // that use them all compute fluxes)
+      if (fin) {
+  #pragma unroll
+        for (int c = 0; c < 5; ++c) fq[c] = qin[c * N + fi];
+        if (mode == kModeStep && a.rk_a != T(0)) {
+  #pragma unroll
+          for (int c = 0; c < 5; ++c) fd[c] = __builtin_nontemporal_load(a.dq + c * N + fi);
+        }
+      }
+      if (__builtin_expect(valid && kcx_d > 0, 0)) {
+        const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsx + opx;
+  #pragma unroll
+        for (int c = 0; c < kNQ; ++c) vfx[c] = at_sum<T>(a, 0, 4 + c, o);
+      }
+      if (__builtin_expect(valid && kcy_d > 0, 0)) {
+        const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsy + opy;
+  #pragma unroll
+        for (int c = 0; c < kNQ; ++c) vfy[c] = at_sum<T>(a, 1, 4 + c, o);
+      }
+
       // stress, pressure and the total fluxes (Eqs. cont, mome, ie in total-energy form), one
       // direction at a time
       const T rho = zw.rho(), u = WIN(0, 2), v = WIN(1, 2), w = WIN(2, 2), t = WIN(3, 2), E = zw.E();
