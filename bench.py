@@ -76,10 +76,10 @@ def build_sim(atns, W, n, pe, precision, n_steps_total, q, dt, mu, fh, tile=None
         b = atns.Batch(precision)
         b.add(sim)
         b.autotune(None, reps=2)
-        t, z = b.get_tuning()
+        shapes = b.get_stage_tuning()  # synchronous and delayed stages
         b.remove(sim)
         b.close()
-        sim.set_tuning(t, z)
+        sim.set_stage_tuning(*shapes)
         tuned = True
     return sim, tuned
 
@@ -195,7 +195,7 @@ def batched_workload(torch, atns, W, steps, warmup, cache):
     for s in sims:
         b.add(s)
     tune_ms = b.autotune(cache, reps=3)
-    tile, zc = b.get_tuning()
+    tile, zc, tile_d, zc_d = b.get_stage_tuning()
     b.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -213,13 +213,14 @@ def batched_workload(torch, atns, W, steps, warmup, cache):
     torch.cuda.empty_cache()
     return {"value": pts * steps / (ms * 1e-3), "unit": "grid-pt-steps/s", "runs": len(specs), "points": pts,
             "steps": steps, "warmup": warmup, "ms_per_step": ms / steps, "tile": tile, "zchunk": zc,
+            "tile_delayed": tile_d, "zchunk_delayed": zc_d,
             "autotune_stage_ms": tune_ms, "graph_captures": caps, "graph_replays": reps,
             "nonfinite_runs": int(nonfinite),
             "workload": "64 runs (16 each of 32^3, 64^3, 96^3, 128^3), CAA/SAA L in 1..3, FP32, one batched "
                         "launch per kernel per RK stage from a HIP graph"}
 
 
-def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64):
+def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64, tile_delayed=-1, zchunk_delayed=64):
     """Poisson arrivals at 20/s for `seconds`; N = 32 round(exp(U(ln 32, ln 256)) / 32); steps ~ U{20..200};
     delays as in the batched workload; request j seeded with 5000 + j.  Initial fields come from a pool of
     two seeded fields per size (building one per request on the host would dominate the latency)."""
@@ -243,7 +244,7 @@ def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64):
         reqs.append(dict(arrival_s=t, n=n, p=2 if n == 32 else n // 32, steps=int(rng.integers(20, 201)),
                          mode=mode, L=L, seed=5000 + j, dt=dt, mu_ref=W.default_mu(n), q0=q))
     res, makespan = atns.serve(reqs, precision="fp32", max_active=64, hbm_budget_bytes=200e9, tile=tile,
-                               zchunk=zchunk)
+                               zchunk=zchunk, tile_delayed=tile_delayed, zchunk_delayed=zchunk_delayed)
     ok = [o for o in res if o["status"] == 0]
     lat = np.array([o["done_s"] - r["arrival_s"] for r, o in zip(reqs, res) if o["status"] == 0])
     work = sum(r["n"] ** 3 * r["steps"] for r, o in zip(reqs, res) if o["status"] == 0)
@@ -252,7 +253,7 @@ def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64):
             "p99_latency_s": float(np.percentile(lat, 99)), "throughput": work / makespan,
             "unit": "grid-pt-steps/s", "offered_load": offered, "makespan_s": makespan,
             "arrival_window_s": seconds, "nonfinite": int(sum(o["stats"]["nonfinite"] for o in ok)),
-            "tile": tile, "zchunk": zchunk,
+            "tile": tile, "zchunk": zchunk, "tile_delayed": tile_delayed, "zchunk_delayed": zchunk_delayed,
             "workload": "Poisson 20/s, N log-uniform 32..256 (multiples of 32), 20..200 steps, CAA/SAA L 1..3, "
                         "FP32, continuous batching"}
 
@@ -304,7 +305,8 @@ def main():
     pd = traffic.delayed_fraction(sched[Wm:Wm + K])
 
     sim, tuned = build_sim(atns, W, n, pe, "fp32", total, q, dt, mu, fh, args.tile, args.zchunk, not args.no_autotune)
-    launch32 = {"tile": sim.get_tuning()[0], "zchunk": sim.get_tuning()[1], "autotuned": tuned}
+    launch32 = dict(zip(("tile", "zchunk", "tile_delayed", "zchunk_delayed"), sim.get_stage_tuning()),
+                    autotuned=tuned)
     log(f"fp32 simulation initialised (launch {launch32}); timing")
     ms32, kt32 = time_steps(torch, sim, Wm, K)
     st32 = sim.stats()
@@ -327,7 +329,7 @@ def main():
            "stats_after": {k: st32[k] for k in ("K", "eps", "enstrophy", "Mt", "nonfinite")}}
     if not args.no_fp64:
         sim, _ = build_sim(atns, W, n, pe, "fp64", total, q, dt, mu, fh, args.tile, args.zchunk, not args.no_autotune)
-        launch64 = {"tile": sim.get_tuning()[0], "zchunk": sim.get_tuning()[1]}
+        launch64 = dict(zip(("tile", "zchunk", "tile_delayed", "zchunk_delayed"), sim.get_stage_tuning()))
         log("fp64 simulation initialised; timing")
         ms64, kt64 = time_steps(torch, sim, Wm, K)
         st64 = sim.stats()
@@ -351,7 +353,8 @@ def main():
         # the launch shape the autotuner chose for the batched mix (same kind of runs), if measured
         bt = out.get("batched", {})
         out["served"] = served_workload(atns, W, args.serve_seconds, tile=bt.get("tile", -1),
-                                        zchunk=bt.get("zchunk", 64))
+                                        zchunk=bt.get("zchunk", 64), tile_delayed=bt.get("tile_delayed", -1),
+                                        zchunk_delayed=bt.get("zchunk_delayed", 64))
         log(f"served: {out['served']}")
     if not args.no_cpu:
         log("cpu oracle baseline ...")

@@ -164,10 +164,20 @@ ATNS_API int at_field_device(at_sim* sim, void** dev_ptr);
  * tile and register budget (0: 64x8, 1: 32x8, 2: 32x8 at higher occupancy, 3: 32x4, 4: 64x4,
  * 5: 16x8, 6: 16x16 points in x-y), `zchunk` (>= 4) the number of z planes each workgroup marches through.
  * Results do not depend on either (every point is computed by the same arithmetic); only speed
- * does.  Set by the autotuner.  Errors: AT_E_INVAL. */
+ * does.  Set by the autotuner.  at_set_tuning sets the shape of every stage, at_get_tuning returns
+ * that of the stages that read no delayed level.  Errors: AT_E_INVAL. */
 #define AT_N_TILES 7
 ATNS_API int at_set_tuning(at_sim* sim, int32_t tile, int32_t zchunk);
 ATNS_API int at_get_tuning(at_sim* sim, int32_t* tile, int32_t* zchunk);
+
+/* Separate launch shapes for the stages that read no delayed level (tile_sync, zchunk_sync) and
+ * for those that do (tile_delayed, zchunk_delayed): the two are compiled differently (the AT code
+ * of Sec. 2.1 is left out of the first), and their fastest shapes differ.  Same meaning and errors
+ * as at_set_tuning. */
+ATNS_API int at_set_stage_tuning(at_sim* sim, int32_t tile_sync, int32_t zchunk_sync, int32_t tile_delayed,
+                                 int32_t zchunk_delayed);
+ATNS_API int at_get_stage_tuning(at_sim* sim, int32_t* tile_sync, int32_t* zchunk_sync, int32_t* tile_delayed,
+                                 int32_t* zchunk_delayed);
 
 /* Kernel timing.  While enabled, every kernel the handle launches is bracketed by two HIP events
  * recorded on the handle's stream; at_kernel_timing synchronises the stream and returns, for kernel
@@ -213,19 +223,23 @@ ATNS_API int at_batch_size(at_batch* batch, int32_t* n_runs);
  * tables do not cover its steps), AT_E_INVAL, AT_E_HIP. */
 ATNS_API int at_batch_step(at_batch* batch, int32_t n_steps);
 
-/* Launch shape of the batched stage launches (same meaning as at_set_tuning; never changes a
- * field value).  Errors: AT_E_INVAL. */
+/* Launch shapes of the batched stage launches (same meaning as at_set_tuning and
+ * at_set_stage_tuning; never change a field value).  Errors: AT_E_INVAL. */
 ATNS_API int at_batch_set_tuning(at_batch* batch, int32_t tile, int32_t zchunk);
 ATNS_API int at_batch_get_tuning(at_batch* batch, int32_t* tile, int32_t* zchunk);
+ATNS_API int at_batch_set_stage_tuning(at_batch* batch, int32_t tile_sync, int32_t zchunk_sync,
+                                       int32_t tile_delayed, int32_t zchunk_delayed);
+ATNS_API int at_batch_get_stage_tuning(at_batch* batch, int32_t* tile_sync, int32_t* zchunk_sync,
+                                       int32_t* tile_delayed, int32_t* zchunk_delayed);
 
-/* Choose the launch shape: looks up the device, the members' shapes and the fraction f of their
+/* Choose the launch shapes: looks up the device, the members' shapes and the fraction f of their
  * remaining scheduled steps that read delayed levels in cache_path (JSON lines; NULL = no cache);
- * otherwise times, for every feasible (tile, z chunk), `reps` synchronous trial stages and `reps`
- * delayed ones (each member at the delays of its first delayed step), keeps the shape with the
- * least (1 - f) t_sync + f t_delayed and appends it to the cache.  A trial rewrites only buffers
+ * otherwise times, for every feasible (tile, z chunk), `reps` synchronous trial stages and (if
+ * f > 0) `reps` delayed ones (each member at the delays of its first delayed step), keeps the
+ * fastest shape of each kind (as at_batch_set_stage_tuning) and appends them to the cache.  A trial rewrites only buffers
  * that are dead between steps (the second state buffer and the RK register) and discards its
- * conserved totals, so the members' states are unchanged.  *best_ms (may be NULL) receives the
- * weighted stage time.  Synchronises.  Errors: AT_E_STATE (empty batch), AT_E_SCHEDULE,
+ * conserved totals, so the members' states are unchanged.  *best_ms (may be NULL) receives
+ * (1 - f) t_sync + f t_delayed of the chosen shapes.  Synchronises.  Errors: AT_E_STATE (empty batch), AT_E_SCHEDULE,
  * AT_E_INVAL, AT_E_HIP. */
 ATNS_API int at_batch_autotune(at_batch* batch, const char* cache_path, int32_t reps, double* best_ms);
 
@@ -251,6 +265,8 @@ typedef struct {
   int32_t max_active;       /* slots: runs served at once */
   int32_t tile, zchunk;     /* batch launch shape (tile < 0: library default) */
   double hbm_budget_bytes;  /* device bytes the server may hold for admitted runs */
+  int32_t tile_delayed, zchunk_delayed; /* shape of the stages that read delayed levels (tile_delayed
+                                           < 0: the same as tile, zchunk) */
 } at_serve_config;
 
 typedef struct {

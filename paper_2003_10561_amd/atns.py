@@ -23,8 +23,10 @@ EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "a
             "at_set_delay_schedule", "at_set_forcing", "at_rhs", "at_rk_step", "at_stats",
             "at_get_field", "at_field_device", "at_destroy", "at_set_kernel_timing",
             "at_kernel_timing", "at_kernel_name", "at_set_tuning", "at_get_tuning",
+            "at_set_stage_tuning", "at_get_stage_tuning",
             "at_batch_create", "at_batch_add", "at_batch_remove", "at_batch_size", "at_batch_step",
-            "at_batch_set_tuning", "at_batch_get_tuning", "at_batch_autotune", "at_batch_set_graph",
+            "at_batch_set_tuning", "at_batch_get_tuning", "at_batch_set_stage_tuning",
+            "at_batch_get_stage_tuning", "at_batch_autotune", "at_batch_set_graph",
             "at_batch_graph_stats", "at_batch_destroy", "at_serve"]
 N_TILES = 7
 N_KERNELS = 6
@@ -54,7 +56,8 @@ class _Stats(C.Structure):
 
 class _ServeConfig(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_active", C.c_int32), ("tile", C.c_int32),
-                ("zchunk", C.c_int32), ("hbm_budget_bytes", C.c_double)]
+                ("zchunk", C.c_int32), ("hbm_budget_bytes", C.c_double), ("tile_delayed", C.c_int32),
+                ("zchunk_delayed", C.c_int32)]
 
 
 class _Request(C.Structure):
@@ -100,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.at_kernel_name.restype = C.c_char_p
     lib.at_set_tuning.argtypes = [vp, i32, i32]
     lib.at_get_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.at_set_stage_tuning.argtypes = [vp, i32, i32, i32, i32]
+    lib.at_get_stage_tuning.argtypes = [vp] + [C.POINTER(C.c_int32)] * 4
     lib.at_batch_create.argtypes = [i32, vp, C.POINTER(vp)]
     lib.at_batch_add.argtypes = [vp, vp]
     lib.at_batch_remove.argtypes = [vp, vp]
@@ -107,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     lib.at_batch_step.argtypes = [vp, i32]
     lib.at_batch_set_tuning.argtypes = [vp, i32, i32]
     lib.at_batch_get_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.at_batch_set_stage_tuning.argtypes = [vp, i32, i32, i32, i32]
+    lib.at_batch_get_stage_tuning.argtypes = [vp] + [C.POINTER(C.c_int32)] * 4
     lib.at_batch_autotune.argtypes = [vp, C.c_char_p, i32, dp]
     lib.at_batch_set_graph.argtypes = [vp, i32]
     lib.at_batch_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -259,6 +266,15 @@ class Sim:
         _check("at_get_tuning", self.lib.at_get_tuning(self.h, C.byref(t), C.byref(z)))
         return int(t.value), int(z.value)
 
+    def set_stage_tuning(self, tile_sync: int, zchunk_sync: int, tile_delayed: int, zchunk_delayed: int):
+        _check("at_set_stage_tuning", self.lib.at_set_stage_tuning(self.h, int(tile_sync), int(zchunk_sync),
+                                                                   int(tile_delayed), int(zchunk_delayed)))
+
+    def get_stage_tuning(self):
+        v = [C.c_int32() for _ in range(4)]
+        _check("at_get_stage_tuning", self.lib.at_get_stage_tuning(self.h, *[C.byref(x) for x in v]))
+        return tuple(int(x.value) for x in v)
+
     def set_kernel_timing(self, enable: bool):
         _check("at_set_kernel_timing", self.lib.at_set_kernel_timing(self.h, int(bool(enable))))
 
@@ -328,6 +344,16 @@ class Batch:
         _check("at_batch_get_tuning", self.lib.at_batch_get_tuning(self.h, C.byref(t), C.byref(z)))
         return int(t.value), int(z.value)
 
+    def set_stage_tuning(self, tile_sync: int, zchunk_sync: int, tile_delayed: int, zchunk_delayed: int):
+        _check("at_batch_set_stage_tuning",
+               self.lib.at_batch_set_stage_tuning(self.h, int(tile_sync), int(zchunk_sync), int(tile_delayed),
+                                                  int(zchunk_delayed)))
+
+    def get_stage_tuning(self):
+        v = [C.c_int32() for _ in range(4)]
+        _check("at_batch_get_stage_tuning", self.lib.at_batch_get_stage_tuning(self.h, *[C.byref(x) for x in v]))
+        return tuple(int(x.value) for x in v)
+
     def autotune(self, cache_path=None, reps: int = 3) -> float:
         ms = C.c_double()
         path = None if cache_path is None else str(cache_path).encode()
@@ -344,7 +370,7 @@ class Batch:
 
 
 def serve(requests, precision: str = "fp32", max_active: int = 64, hbm_budget_bytes: float = 64e9,
-          tile: int = -1, zchunk: int = 64, stream=None):
+          tile: int = -1, zchunk: int = 64, stream=None, tile_delayed: int = -1, zchunk_delayed: int = 64):
     """Serve a request trace with continuous batching (at_serve).  Each request is a dict with
     arrival_s, n, p, steps, mode, L, seed, dt, mu_ref, q0 (float64 [5][n][n][n]) and optionally
     q_final (a float64 array of the same shape that receives the final state).  Returns
@@ -353,7 +379,7 @@ def serve(requests, precision: str = "fp32", max_active: int = 64, hbm_budget_by
     lib = load_library()
     st = stream if stream is not None else torch.cuda.current_stream()
     sc = _ServeConfig(FP32 if precision == "fp32" else FP64, int(max_active), int(tile), int(zchunk),
-                      float(hbm_budget_bytes))
+                      float(hbm_budget_bytes), int(tile_delayed), int(zchunk_delayed))
     n = len(requests)
     reqs = (_Request * max(n, 1))()
     keep = []

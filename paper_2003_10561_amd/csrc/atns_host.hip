@@ -236,7 +236,7 @@ template <typename T>
 hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode, bool at) {
   const int id = mode == kModeStepH ? kKStage : (mode == kModeRhsH ? kKRhs : kKPublish);
   if (s->timer) s->timer->before(id, s->stream);
-  hipError_t e = launch_fused<T>(a, s->tile, s->zchunk, mode, at, s->stream);
+  hipError_t e = launch_fused<T>(a, at ? s->tile_d : s->tile, at ? s->zchunk_d : s->zchunk, mode, at, s->stream);
   if (s->timer) s->timer->after(id, s->stream);
   return e;
 }
@@ -299,7 +299,8 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
 template <typename T>
 int do_steps(at_sim* s, int nsteps) {
   const size_t row = (size_t)s->g.ntiles * 6;
-  if (nsteps > 0) s->tot_used = std::max(s->tot_used, fused_blocks(s->g, s->tile, s->zchunk));
+  if (nsteps > 0)
+    s->tot_used = std::max({s->tot_used, fused_blocks(s->g, s->tile, s->zchunk), fused_blocks(s->g, s->tile_d, s->zchunk_d)});
   for (int it = 0; it < nsteps; ++it) {
     StageArgs<T> a = base_args<T>(s);
     a.delays = s->d_sched + (size_t)s->step * row;
@@ -394,6 +395,8 @@ int at_create(const at_config* cfg, void* ws, size_t ws_bytes, void* stream, at_
   s->tile = fused_lds_bytes(1, cfg->precision == AT_FP32 ? 4 : 8, cfg->forcing != 0) <= kLdsBytes ? 1 : 5;
   s->zchunk = cfg->n[2] / cfg->p[2] >= 16 ? cfg->n[2] / cfg->p[2] : cfg->n[2];
   if (s->zchunk > 128) s->zchunk = 128;
+  s->tile_d = s->tile;
+  s->zchunk_d = s->zchunk;
   hipError_t e = hipGetDevice(&s->device);
   if (e == hipSuccess) e = hipMalloc(&s->d_zero, (size_t)g.ntiles * 6);
   if (e == hipSuccess) e = hipMemsetAsync(s->d_zero, 0, (size_t)g.ntiles * 6, s->stream);
@@ -557,16 +560,42 @@ int at_field_device(at_sim* s, void** ptr) {
   return AT_OK;
 }
 
-int at_set_tuning(at_sim* s, int32_t tile, int32_t zchunk) {
-  if (!s) return fail(AT_E_INVAL, "NULL handle");
+namespace {
+int check_shape(const at_sim* s, int32_t tile, int32_t zchunk) {
   if (tile < 0 || tile >= kTileCount) return fail(AT_E_INVAL, "unknown tile shape");
   if (zchunk < 4) return fail(AT_E_INVAL, "z chunk must be >= 4");
   const size_t word = s->cfg.precision == AT_FP32 ? 4 : 8;
   if (fused_lds_bytes(tile, word, s->cfg.forcing != 0) > kLdsBytes)
     return fail(AT_E_INVAL, "tile shape needs more LDS than a compute unit has at this precision");
-  s->tile = tile;
-  s->zchunk = zchunk > s->cfg.n[2] ? s->cfg.n[2] : zchunk;
   return AT_OK;
+}
+}  // namespace
+
+int at_set_stage_tuning(at_sim* s, int32_t tile_sync, int32_t zchunk_sync, int32_t tile_delayed,
+                        int32_t zchunk_delayed) {
+  if (!s) return fail(AT_E_INVAL, "NULL handle");
+  int rc = check_shape(s, tile_sync, zchunk_sync);
+  if (!rc) rc = check_shape(s, tile_delayed, zchunk_delayed);
+  if (rc) return rc;
+  s->tile = tile_sync;
+  s->zchunk = std::min(zchunk_sync, s->cfg.n[2]);
+  s->tile_d = tile_delayed;
+  s->zchunk_d = std::min(zchunk_delayed, s->cfg.n[2]);
+  return AT_OK;
+}
+
+int at_get_stage_tuning(at_sim* s, int32_t* tile_sync, int32_t* zchunk_sync, int32_t* tile_delayed,
+                        int32_t* zchunk_delayed) {
+  if (!s || !tile_sync || !zchunk_sync || !tile_delayed || !zchunk_delayed) return fail(AT_E_INVAL, "NULL argument");
+  *tile_sync = s->tile;
+  *zchunk_sync = s->zchunk;
+  *tile_delayed = s->tile_d;
+  *zchunk_delayed = s->zchunk_d;
+  return AT_OK;
+}
+
+int at_set_tuning(at_sim* s, int32_t tile, int32_t zchunk) {
+  return at_set_stage_tuning(s, tile, zchunk, tile, zchunk);
 }
 
 int at_get_tuning(at_sim* s, int32_t* tile, int32_t* zchunk) {

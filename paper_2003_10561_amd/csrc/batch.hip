@@ -29,7 +29,8 @@ struct at_batch {
   hipStream_t cap = nullptr;     // private stream, used only to capture graphs
   int device = 0;
   std::vector<at_sim*> runs;
-  int tile = 1, zchunk = 64;
+  int tile = 1, zchunk = 64;      // launch shape of the stages that read no delayed level
+  int tile_d = 1, zchunk_d = 64;  // and of those that do
   int use_graph = 1;
   // device buffer of one chunk: [stage work][view work][forcing rows][run tables]
   uint8_t* d_buf = nullptr;
@@ -55,7 +56,9 @@ constexpr size_t kFhatRow = (size_t)kNForce * 6;  // doubles of one step's forci
 
 size_t word_of(int precision) { return precision == AT_FP32 ? 4 : 8; }
 
-int run_zchunk(const at_batch* b, const at_sim* s) { return std::min(b->zchunk, s->cfg.n[2]); }
+// Launch shape of kind k (0: stages that read no delayed level, 1: those that do).
+int kind_tile(const at_batch* b, int k) { return k ? b->tile_d : b->tile; }
+int run_zchunk(const at_batch* b, const at_sim* s, int k) { return std::min(k ? b->zchunk_d : b->zchunk, s->cfg.n[2]); }
 
 bool any_forced(const at_batch* b) {
   for (const at_sim* s : b->runs)
@@ -81,11 +84,11 @@ void drop_graph(at_batch* b) {
 // Placement of one chunk's tables in the device buffer.
 struct ChunkPlan {
   int K = 0;
-  int64_t nsw = 0, nvw = 0;  // stage / view work-list entries
-  bool views = false;        // launch the batched AT sums at every stage
+  int64_t nsw[2] = {0, 0}, nvw = 0;  // stage work-list entries of either launch shape; view entries
+  bool views = false;                 // launch the batched AT sums and AT stages at every stage
   std::vector<int> forced;   // indices of forced runs
 
-  size_t off_sw = 0, off_vw = 0, off_fh = 0, off_args = 0, total = 0, argb = 0;
+  size_t off_sw[2] = {0, 0}, off_vw = 0, off_fh = 0, off_args[2] = {0, 0}, total = 0, argb = 0;
 };
 
 ChunkPlan plan_chunk(const at_batch* b, int K) {
@@ -94,7 +97,8 @@ ChunkPlan plan_chunk(const at_batch* b, int K) {
   p.argb = b->precision == AT_FP32 ? batch_arg_bytes<float>() : batch_arg_bytes<double>();
   for (size_t m = 0; m < b->runs.size(); ++m) {
     const at_sim* s = b->runs[m];
-    p.nsw += fused_blocks(s->g, b->tile, run_zchunk(b, s));
+    p.nsw[0] += fused_blocks(s->g, b->tile, run_zchunk(b, s, 0));
+    p.nsw[1] += fused_blocks(s->g, b->tile_d, run_zchunk(b, s, 1));
     if (ever_delayed(s)) {
       p.views = true;
       p.nvw += view_blocks(s->g);
@@ -102,15 +106,20 @@ ChunkPlan plan_chunk(const at_batch* b, int K) {
     if (s->cfg.forcing) p.forced.push_back((int)m);
   }
 
+  if (!p.views) p.nsw[1] = 0;
   size_t off = 0;
-  p.off_sw = off;
-  off = align_up(off + (size_t)p.nsw * sizeof(uint2));
+  for (int k = 0; k < 2; ++k) {
+    p.off_sw[k] = off;
+    off = align_up(off + (size_t)p.nsw[k] * sizeof(uint2));
+  }
   p.off_vw = off;
   off = align_up(off + (size_t)p.nvw * sizeof(uint2));
   p.off_fh = off;
   off = align_up(off + p.forced.size() * (size_t)K * kFhatRow * sizeof(double));
-  p.off_args = off;
-  off = align_up(off + (size_t)K * 3 * b->runs.size() * p.argb);
+  for (int k = 0; k < 2; ++k) {
+    p.off_args[k] = off;
+    if (k == 0 || p.views) off = align_up(off + (size_t)K * 3 * b->runs.size() * p.argb);
+  }
   p.total = off;
   return p;
 }
@@ -175,13 +184,16 @@ StageArgs<T> chunk_args(at_sim* s, int bstep, int st, double* tot_override) {
 // Work lists and run tables of a chunk of K steps into host staging.
 template <typename T>
 void fill_chunk(at_batch* b, const ChunkPlan& p, uint8_t* h) {
-  uint2* sw = (uint2*)(h + p.off_sw);
+  const int nk = p.views ? 2 : 1;
   uint2* vw = (uint2*)(h + p.off_vw);
-  int64_t is = 0, iv = 0;
+  int64_t is[2] = {0, 0}, iv = 0;
   for (size_t m = 0; m < b->runs.size(); ++m) {
     const at_sim* s = b->runs[m];
-    const int64_t nb = fused_blocks(s->g, b->tile, run_zchunk(b, s));
-    for (int64_t k = 0; k < nb; ++k) sw[is++] = make_uint2((unsigned)m, (unsigned)k);
+    for (int kd = 0; kd < nk; ++kd) {
+      uint2* sw = (uint2*)(h + p.off_sw[kd]);
+      const int64_t nb = fused_blocks(s->g, kind_tile(b, kd), run_zchunk(b, s, kd));
+      for (int64_t k = 0; k < nb; ++k) sw[is[kd]++] = make_uint2((unsigned)m, (unsigned)k);
+    }
     if (ever_delayed(s)) {
       const int64_t nv = view_blocks(s->g);
       for (int64_t k = 0; k < nv; ++k) vw[iv++] = make_uint2((unsigned)m, (unsigned)k);
@@ -200,7 +212,9 @@ void fill_chunk(at_batch* b, const ChunkPlan& p, uint8_t* h) {
         at_sim* s = b->runs[m];
         const StageArgs<T> a = chunk_args<T>(s, bs, st, nullptr);
         const int views = s->step_delayed[(size_t)(s->step + bs)] ? 1 : 0;
-        pack_batch_arg<T>(a, b->tile, run_zchunk(b, s), views, h + p.off_args + ((size_t)(bs * 3 + st) * M + m) * p.argb);
+        for (int kd = 0; kd < nk; ++kd)
+          pack_batch_arg<T>(a, kind_tile(b, kd), run_zchunk(b, s, kd), views,
+                            h + p.off_args[kd] + ((size_t)(bs * 3 + st) * M + m) * p.argb);
       }
 }
 
@@ -209,7 +223,8 @@ template <typename T>
 hipError_t enqueue_chunk(at_batch* b, const ChunkPlan& p, hipStream_t st) {
   const size_t M = b->runs.size();
   const bool forced = !p.forced.empty();
-  const uint2* sw = (const uint2*)(b->d_buf + p.off_sw);
+  const uint2* sw = (const uint2*)(b->d_buf + p.off_sw[0]);
+  const uint2* swd = (const uint2*)(b->d_buf + p.off_sw[1]);
   const uint2* vw = (const uint2*)(b->d_buf + p.off_vw);
   const double* fh = (const double*)(b->d_buf + p.off_fh);
   for (int bs = 0; bs < p.K; ++bs) {
@@ -221,19 +236,20 @@ hipError_t enqueue_chunk(at_batch* b, const ChunkPlan& p, hipStream_t st) {
       if (e != hipSuccess) return e;
     }
     for (int stg = 0; stg < 3; ++stg) {
-      const void* tab = b->d_buf + p.off_args + (size_t)(bs * 3 + stg) * M * p.argb;
+      const void* tab = b->d_buf + p.off_args[0] + (size_t)(bs * 3 + stg) * M * p.argb;
+      const void* tabd = b->d_buf + p.off_args[1] + (size_t)(bs * 3 + stg) * M * p.argb;
       if (p.views && p.nvw > 0) {
         hipError_t e = launch_at_sums_batch<T>(tab, vw, p.nvw, st);
         if (e != hipSuccess) return e;
       }
-      // runs that read delayed levels at this step run the AT instantiation, the others the
-      // plain one (each leaves the other's launch at once); both are launched at every stage of a
-      // batch with any delayed schedule, so that a chunk's graph depends only on membership,
-      // launch shape and length
-      hipError_t e = launch_fused_batch<T>(tab, sw, p.nsw, b->tile, forced, stg == 0, false, kModeStepH, st);
+      // runs that read delayed levels at this step run the AT instantiation (in its own launch
+      // shape), the others the plain one (each leaves the other's launch at once); both are
+      // launched at every stage of a batch with any delayed schedule, so that a chunk's graph
+      // depends only on membership, launch shapes and length
+      hipError_t e = launch_fused_batch<T>(tab, sw, p.nsw[0], b->tile, forced, stg == 0, false, kModeStepH, st);
       if (e != hipSuccess) return e;
       if (p.views) {
-        e = launch_fused_batch<T>(tab, sw, p.nsw, b->tile, forced, stg == 0, true, kModeStepH, st);
+        e = launch_fused_batch<T>(tabd, swd, p.nsw[1], b->tile_d, forced, stg == 0, true, kModeStepH, st);
         if (e != hipSuccess) return e;
       }
     }
@@ -242,9 +258,11 @@ hipError_t enqueue_chunk(at_batch* b, const ChunkPlan& p, hipStream_t st) {
 }
 
 std::vector<uint64_t> chunk_signature(const at_batch* b, const ChunkPlan& p) {
-  std::vector<uint64_t> sg = {(uint64_t)b->tile, (uint64_t)b->zchunk, (uint64_t)p.K, (uint64_t)b->precision,
-                              (uint64_t)(uintptr_t)b->d_buf, (uint64_t)p.nsw, (uint64_t)p.nvw, (uint64_t)p.views,
-                              (uint64_t)p.off_args, (uint64_t)p.off_fh, (uint64_t)p.off_vw};
+  std::vector<uint64_t> sg = {(uint64_t)b->tile, (uint64_t)b->zchunk, (uint64_t)b->tile_d, (uint64_t)b->zchunk_d,
+                              (uint64_t)p.K, (uint64_t)b->precision, (uint64_t)(uintptr_t)b->d_buf,
+                              (uint64_t)p.nsw[0], (uint64_t)p.nsw[1], (uint64_t)p.nvw, (uint64_t)p.views,
+                              (uint64_t)p.off_args[0], (uint64_t)p.off_args[1], (uint64_t)p.off_fh,
+                              (uint64_t)p.off_vw};
   for (const at_sim* s : b->runs) {
     sg.push_back((uint64_t)(uintptr_t)s);
     sg.push_back((uint64_t)s->cfg.forcing);
@@ -285,7 +303,8 @@ int do_batch_steps(at_batch* b, int K) {
     HIP_TRY(enqueue_chunk<T>(b, p, b->stream));
   }
   for (at_sim* s : b->runs) {
-    s->tot_used = std::max(s->tot_used, fused_blocks(s->g, b->tile, run_zchunk(b, s)));
+    s->tot_used = std::max({s->tot_used, fused_blocks(s->g, b->tile, run_zchunk(b, s, 0)),
+                            fused_blocks(s->g, b->tile_d, run_zchunk(b, s, 1))});
     s->step += K;
     s->qcur ^= (K & 1);
   }
@@ -306,18 +325,21 @@ int64_t first_delayed_step(const at_sim* s) {
 // RK register.
 template <typename T>
 int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, double* ms) {
-  const int t0 = b->tile, z0 = b->zchunk;
-  b->tile = tile;
-  b->zchunk = zchunk;
+  // both kinds of stage in the trial shape; the tables of kind 0 serve both launches
+  const int t0 = b->tile, z0 = b->zchunk, t1 = b->tile_d, z1 = b->zchunk_d;
+  b->tile = b->tile_d = tile;
+  b->zchunk = b->zchunk_d = zchunk;
   const ChunkPlan p = plan_chunk(b, 1);
   b->tile = t0;
   b->zchunk = z0;
+  b->tile_d = t1;
+  b->zchunk_d = z1;
   const int slot = b->h_next;
   int rc = ensure_buffers(b, p.total, slot);
   if (rc) return rc;
   HIP_TRY(wait_staging(b, slot));
   uint8_t* h = b->h_buf[slot];
-  uint2* sw = (uint2*)(h + p.off_sw);
+  uint2* sw = (uint2*)(h + p.off_sw[0]);
   int64_t is = 0;
   size_t tot_off = 0;
   bool any_at = false;
@@ -339,16 +361,17 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, doubl
       views = 1;
       any_at = true;
     }
-    pack_batch_arg<T>(a, tile, zc, views, h + p.off_args + m * p.argb);
+    pack_batch_arg<T>(a, tile, zc, views, h + p.off_args[0] + m * p.argb);
   }
   HIP_TRY(upload(b, slot, p.total));
   const bool forced = !p.forced.empty();
-  const void* tab = b->d_buf + p.off_args;
-  const uint2* dsw = (const uint2*)(b->d_buf + p.off_sw);
+  const void* tab = b->d_buf + p.off_args[0];
+  const uint2* dsw = (const uint2*)(b->d_buf + p.off_sw[0]);
   const bool at = any_at;
   auto trial = [&]() -> hipError_t {
-    hipError_t e = launch_fused_batch<T>(tab, dsw, p.nsw, tile, forced, false, false, kModeStepH, b->stream);
-    if (e == hipSuccess && at) e = launch_fused_batch<T>(tab, dsw, p.nsw, tile, forced, false, true, kModeStepH, b->stream);
+    hipError_t e = launch_fused_batch<T>(tab, dsw, p.nsw[0], tile, forced, false, false, kModeStepH, b->stream);
+    if (e == hipSuccess && at)
+      e = launch_fused_batch<T>(tab, dsw, p.nsw[0], tile, forced, false, true, kModeStepH, b->stream);
     return e;
   };
   HIP_TRY(trial());
@@ -397,8 +420,10 @@ std::string tune_key(const at_batch* b) {
   return k.str();
 }
 
-// Cache file: one JSON object per line, {"key": "...", "tile": t, "zchunk": z, "ms": m}.
-bool cache_lookup(const char* path, const std::string& key, int* tile, int* zchunk, double* ms) {
+// Cache file: one JSON object per line, {"key": "...", "tile": t, "zchunk": z, "tile_delayed": td,
+// "zchunk_delayed": zd, "ms": m} (a line without the delayed shape gives both kinds (t, z)).
+bool cache_lookup(const char* path, const std::string& key, int* tile, int* zchunk, int* tile_d, int* zchunk_d,
+                  double* ms) {
   if (!path) return false;
   std::ifstream f(path);
   std::string line;
@@ -414,19 +439,30 @@ bool cache_lookup(const char* path, const std::string& key, int* tile, int* zchu
         std::sscanf(line.c_str() + pm + 6, "%lf", &m) != 1)
       continue;
     if (t < 0 || t >= kTileCount || z < 4) continue;
+    int td = t, zd = z;
+    const size_t ptd = line.find("\"tile_delayed\": "), pzd = line.find("\"zchunk_delayed\": ");
+    if (ptd != std::string::npos && pzd != std::string::npos &&
+        (std::sscanf(line.c_str() + ptd + 16, "%d", &td) != 1 || std::sscanf(line.c_str() + pzd + 18, "%d", &zd) != 1 ||
+         td < 0 || td >= kTileCount || zd < 4))
+      continue;
     *tile = t;
     *zchunk = z;
+    *tile_d = td;
+    *zchunk_d = zd;
     *ms = m;
     found = true;  // the last matching line wins
   }
   return found;
 }
 
-void cache_store(const char* path, const std::string& key, int tile, int zchunk, double ms) {
+void cache_store(const char* path, const std::string& key, int tile, int zchunk, int tile_d, int zchunk_d,
+                 double ms) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  char buf[128];
-  std::snprintf(buf, sizeof(buf), "\", \"tile\": %d, \"zchunk\": %d, \"ms\": %.17g}\n", tile, zchunk, ms);
+  char buf[192];
+  std::snprintf(buf, sizeof(buf),
+                "\", \"tile\": %d, \"zchunk\": %d, \"tile_delayed\": %d, \"zchunk_delayed\": %d, \"ms\": %.17g}\n",
+                tile, zchunk, tile_d, zchunk_d, ms);
   f << "{\"key\": \"" << key << buf;
 }
 
@@ -441,19 +477,22 @@ double delayed_fraction(const at_batch* b) {
   return tot > 0.0 ? del / tot : 0.0;
 }
 
-// Launch shape from timed trial stages: for every feasible (tile, z chunk) the synchronous and
-// the delayed trial, weighted by the fraction of remaining steps that read delayed levels.
+// Launch shapes from timed trial stages: for every feasible (tile, z chunk) the synchronous and
+// (if any remaining step reads delayed levels) the delayed trial; the fastest shape of each kind.
+// The reported time weights the two by the fraction of remaining steps that read delayed levels.
 template <typename T>
 int do_autotune(at_batch* b, const char* cache, int reps, double* best_ms) {
   const double f = delayed_fraction(b);
   char fbuf[32];
   std::snprintf(fbuf, sizeof(fbuf), "|delayed=%.2f", f);
   const std::string key = tune_key(b) + fbuf;
-  int t = -1, z = -1;
+  int t = -1, z = -1, td = -1, zd = -1;
   double ms = 0.0;
-  if (cache_lookup(cache, key, &t, &z, &ms) && tile_fits(b, t)) {
+  if (cache_lookup(cache, key, &t, &z, &td, &zd, &ms) && tile_fits(b, t) && tile_fits(b, td)) {
     b->tile = t;
     b->zchunk = z;
+    b->tile_d = td;
+    b->zchunk_d = zd;
     if (best_ms) *best_ms = ms;
     return AT_OK;
   }
@@ -469,8 +508,8 @@ int do_autotune(at_batch* b, const char* cache, int reps, double* best_ms) {
   }
   int maxz = 4;
   for (const at_sim* s : b->runs) maxz = std::max(maxz, s->cfg.n[2]);
-  double best = 1e300;
-  int bt = b->tile, bz = b->zchunk;
+  double best_s = 1e300, best_d = 1e300;
+  int bt = b->tile, bz = b->zchunk, btd = b->tile_d, bzd = b->zchunk_d;
   static const int kZ[] = {8, 16, 32, 64, 128};
   for (int tile = 0; tile < kTileCount; ++tile) {
     if (!tile_fits(b, tile)) continue;
@@ -480,18 +519,30 @@ int do_autotune(at_batch* b, const char* cache, int reps, double* best_ms) {
       int rc = trial_stage<T>(b, tile, zc, reps, false, &m_sync);
       if (!rc && f > 0.0) rc = trial_stage<T>(b, tile, zc, reps, true, &m_at);
       if (rc) return rc;
-      const double m = (1.0 - f) * m_sync + f * m_at;
-      if (m < best) {
-        best = m;
+      if (m_sync < best_s) {
+        best_s = m_sync;
         bt = tile;
         bz = zc;
       }
+      if (f > 0.0 && m_at < best_d) {
+        best_d = m_at;
+        btd = tile;
+        bzd = zc;
+      }
     }
+  }
+  if (!(f > 0.0)) {  // no delayed stage ahead: both kinds in the synchronous choice
+    btd = bt;
+    bzd = bz;
+    best_d = 0.0;
   }
   b->tile = bt;
   b->zchunk = bz;
+  b->tile_d = btd;
+  b->zchunk_d = bzd;
+  const double best = (1.0 - f) * best_s + f * best_d;
   if (best_ms) *best_ms = best;
-  cache_store(cache, key, bt, bz, best);
+  cache_store(cache, key, bt, bz, btd, bzd, best);
   return AT_OK;
 }
 
@@ -514,7 +565,7 @@ int at_batch_create(int32_t precision, void* stream, at_batch** out) {
   if (!b) return fail(AT_E_INVAL, "out of host memory");
   b->precision = precision;
   b->stream = (hipStream_t)stream;
-  b->tile = fused_lds_bytes(1, word_of(precision), false) <= kLdsBytes ? 1 : 5;
+  b->tile = b->tile_d = fused_lds_bytes(1, word_of(precision), false) <= kLdsBytes ? 1 : 5;
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&b->h_done[i], hipEventDisableTiming);
@@ -534,7 +585,8 @@ int at_batch_add(at_batch* b, at_sim* s) {
   if (s->stream != b->stream) return fail(AT_E_INVAL, "run and batch must use the same stream");
   if (s->device != b->device) return fail(AT_E_INVAL, "run and batch must be on the same device");
   if ((int)b->runs.size() >= kMaxBatchRuns) return fail(AT_E_INVAL, "batch is full");
-  if (s->cfg.forcing && fused_lds_bytes(b->tile, word_of(b->precision), true) > kLdsBytes)
+  if (s->cfg.forcing && (fused_lds_bytes(b->tile, word_of(b->precision), true) > kLdsBytes ||
+                         fused_lds_bytes(b->tile_d, word_of(b->precision), true) > kLdsBytes))
     return fail(AT_E_INVAL, "the batch's tile shape does not fit a forced run; set a smaller tile first");
   b->runs.push_back(s);
   s->batch = b;
@@ -569,14 +621,34 @@ int at_batch_step(at_batch* b, int32_t n_steps) {
   return b->precision == AT_FP32 ? do_batch_steps<float>(b, n_steps) : do_batch_steps<double>(b, n_steps);
 }
 
-int at_batch_set_tuning(at_batch* b, int32_t tile, int32_t zchunk) {
+int at_batch_set_stage_tuning(at_batch* b, int32_t tile_sync, int32_t zchunk_sync, int32_t tile_delayed,
+                              int32_t zchunk_delayed) {
   if (!b) return fail(AT_E_INVAL, "NULL handle");
-  if (tile < 0 || tile >= kTileCount) return fail(AT_E_INVAL, "unknown tile shape");
-  if (zchunk < 4) return fail(AT_E_INVAL, "z chunk must be >= 4");
-  if (!tile_fits(b, tile)) return fail(AT_E_INVAL, "tile shape needs more LDS than a compute unit has");
-  b->tile = tile;
-  b->zchunk = zchunk;
+  for (int k = 0; k < 2; ++k) {
+    const int32_t tile = k ? tile_delayed : tile_sync, zchunk = k ? zchunk_delayed : zchunk_sync;
+    if (tile < 0 || tile >= kTileCount) return fail(AT_E_INVAL, "unknown tile shape");
+    if (zchunk < 4) return fail(AT_E_INVAL, "z chunk must be >= 4");
+    if (!tile_fits(b, tile)) return fail(AT_E_INVAL, "tile shape needs more LDS than a compute unit has");
+  }
+  b->tile = tile_sync;
+  b->zchunk = zchunk_sync;
+  b->tile_d = tile_delayed;
+  b->zchunk_d = zchunk_delayed;
   return AT_OK;
+}
+
+int at_batch_get_stage_tuning(at_batch* b, int32_t* tile_sync, int32_t* zchunk_sync, int32_t* tile_delayed,
+                              int32_t* zchunk_delayed) {
+  if (!b || !tile_sync || !zchunk_sync || !tile_delayed || !zchunk_delayed) return fail(AT_E_INVAL, "NULL argument");
+  *tile_sync = b->tile;
+  *zchunk_sync = b->zchunk;
+  *tile_delayed = b->tile_d;
+  *zchunk_delayed = b->zchunk_d;
+  return AT_OK;
+}
+
+int at_batch_set_tuning(at_batch* b, int32_t tile, int32_t zchunk) {
+  return at_batch_set_stage_tuning(b, tile, zchunk, tile, zchunk);
 }
 
 int at_batch_get_tuning(at_batch* b, int32_t* tile, int32_t* zchunk) {

@@ -128,7 +128,9 @@ extern "C" int at_serve(const at_serve_config* sc, const at_request* reqs, int32
   int rc = at_batch_create(sc->precision, hip_stream, &batch);
   if (rc) return rc;
   if (sc->tile >= 0) {
-    rc = at_batch_set_tuning(batch, sc->tile, sc->zchunk);
+    rc = sc->tile_delayed >= 0
+             ? at_batch_set_stage_tuning(batch, sc->tile, sc->zchunk, sc->tile_delayed, sc->zchunk_delayed)
+             : at_batch_set_tuning(batch, sc->tile, sc->zchunk);
     if (rc) {
       at_batch_destroy(batch);
       return rc;

@@ -60,8 +60,10 @@ struct at_sim {
   int64_t step = 0;
   int initialised = 0;
   int qcur = 0;                 // which state buffer holds the current state
-  int tile = 1;                 // fused-stage launch shape (index into tile_shape)
-  int zchunk = 64;              // fused-stage z chunk
+  int tile = 1;                 // fused-stage launch shape (index into tile_shape) and z chunk of
+  int zchunk = 64;              // the stages that read no delayed level
+  int tile_d = 1;               // the same for the stages that read delayed levels
+  int zchunk_d = 64;
   double tot_init[atns::kNQ];
   int64_t tot_used = 0;               // FP64 total slots written by stage launches so far
   atns::EventTimer* timer = nullptr;  // non-null while kernel timing is enabled

@@ -154,6 +154,35 @@ def test_launch_shape_does_not_change_fields(precision):
             assert st["mass_rk"] == pytest.approx(ref[1]["mass_rk"], rel=1e-13)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_separate_stage_shapes(precision):
+    """Synchronous and delayed stages in different launch shapes: a batch equals its members
+    stepped alone with the same two shapes bit for bit (fields and statistics), and the fields
+    equal those of a single shape for every stage."""
+    say(f"case stage shapes {precision}")
+    shapes = (3, 16, 5, 8) if precision == "fp64" else (0, 16, 5, 8)  # z chunks within every grid
+    b = atns.Batch(precision)
+    b.set_stage_tuning(*shapes)
+    assert b.get_stage_tuning() == shapes
+    assert b.get_tuning() == shapes[:2]
+    batched = [make_run(i, r, precision)[0] for i, r in enumerate(RUNS[:3])]
+    solo = [make_run(i, r, precision)[0] for i, r in enumerate(RUNS[:3])]
+    single = [make_run(i, r, precision, (5, 64))[0] for i, r in enumerate(RUNS[:3])]
+    for s in solo:
+        s.set_stage_tuning(*shapes)
+        assert s.get_stage_tuning() == shapes
+    for s in batched:
+        b.add(s)
+    for chunk in (3, 5):
+        b.step(chunk)
+        for s in solo + single:
+            s.rk_step(chunk)
+        for i in range(3):
+            assert_same(batched[i], solo[i], f"run {i} after chunk {chunk}")
+            assert np.array_equal(batched[i].get_field(), single[i].get_field()), i
+    b.close()
+
+
 def test_autotune_keeps_state_and_uses_cache(tmp_path):
     say("case autotune")
     cache = tmp_path / "tune.jsonl"
@@ -181,6 +210,7 @@ def test_autotune_keeps_state_and_uses_cache(tmp_path):
     b2.set_tuning(5, 8)
     assert b2.autotune(cache, reps=2) == pytest.approx(ms)
     assert b2.get_tuning() == (tile, zc)
+    assert b2.get_stage_tuning() == b.get_stage_tuning()
     assert cache.read_text().count("\n") == 1
 
 
