@@ -96,7 +96,7 @@ Layout make_layout(const at_config* c, const Geom& g) {
   L.q[1] = take(kNQ * N * w);
   L.dq = take(kNQ * N * w);
   L.ring = take((size_t)g.R * g.ring_slot * w);
-  L.gv = take((size_t)g.ring_slot * w);
+  L.gv = take((size_t)3 * g.ring_slot * w);  // the AT sums of the three stages of a step
   // smallest tile (16 x 4) and smallest z chunk (4) bound the workgroup count of any stage launch
   L.ntot = (int64_t)((c->n[0] + 15) / 16) * ((c->n[1] + 3) / 4) * ((c->n[2] + 3) / 4);
   L.tot_part = take((size_t)L.ntot * kNQ * 8);
@@ -244,7 +244,7 @@ hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode, bool at) {
 template <typename T>
 hipError_t launch_views(at_sim* s, const StageArgs<T>& a) {
   if (s->timer) s->timer->before(kKGhost, s->stream);
-  hipError_t e = launch_at_sums<T>(a, s->stream);
+  hipError_t e = launch_at_sums<T>(a, kRkC, s->stream);
   if (s->timer) s->timer->after(kKGhost, s->stream);
   return e;
 }
@@ -277,7 +277,6 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
       a.delays = s->d_zero;
       a.step = lev;
       a.step_mod_r = (int)(lev % s->g.R);
-      a.cstage = T(0);
       a.publish = 1;
       HIP_TRY(launch_hooked<T>(s, a, kModePublishH, false));
     }
@@ -316,12 +315,13 @@ int do_steps(at_sim* s, int nsteps) {
     for (int st = 0; st < 3; ++st) {
       a.q = (T*)(s->ws + s->L.q[s->qcur]);
       a.q_out = (T*)(s->ws + s->L.q[1 - s->qcur]);
-      a.cstage = (T)kRkC[st];
+      a.gv = a.gv_out + (size_t)st * s->g.ring_slot;
       a.rk_a = (T)kRkA[st];
       a.rk_b = (T)kRkB[st];
       a.publish = st == 0;
       a.store_dq = st < 2;
-      if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
+      // the AT sums of all three stages, once per step that reads delayed levels
+      if (st == 0 && s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
       HIP_TRY(launch_hooked<T>(s, a, kModeStepH, s->step_delayed[(size_t)s->step] != 0));
       s->qcur = 1 - s->qcur;
     }
@@ -336,7 +336,6 @@ int do_rhs(at_sim* s, void* out) {
   a.delays = s->d_sched + (size_t)s->step * s->g.ntiles * 6;
   a.step = s->step;
   a.step_mod_r = (int)(s->step % s->g.R);
-  a.cstage = T(0);
   a.rk_a = T(0);
   a.rk_b = T(0);
   a.publish = 0;

@@ -64,13 +64,13 @@ struct StageArgs {
   T* q_out;           // conserved state written by the stage (the other buffer)
   T* dq;              // RK register [5][N]
   T* ring;            // ring base
-  T* gv_out;          // AT sums of the face-layer readers for this stage (written by k_at_sums)
-  const T* gv;        // the same buffer, read by the stage kernel
+  T* gv_out;          // AT sums of the face-layer readers, three slot-sized regions (one per stage
+                      // of the step), written by k_at_sums
+  const T* gv;        // the region of this stage, read by the stage kernel
   T* rhs_out;         // RHS-only mode output [5][N] (null in stepping mode)
   const int8_t* delays;  // [ntiles][6] for this step
   int64_t step;       // absolute step index n
   int step_mod_r;     // n mod R: ring slot of level n
-  T cstage;           // c_s of this stage
   T rk_a, rk_b, dt;
   int publish;        // stage 1: write level n into the ring
   int store_dq;       // 0 in the last stage (the register is not read again)
@@ -103,7 +103,7 @@ size_t fused_lds_bytes(int tile, size_t word, bool forced);
 template <typename T>
 hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, bool at, hipStream_t stream);
 template <typename T>
-hipError_t launch_at_sums(const StageArgs<T>& a, hipStream_t stream);
+hipError_t launch_at_sums(const StageArgs<T>& a, const double* cs, hipStream_t stream);  // cs: c_s of stages 1-3
 
 // Batched launches (one launch over the workgroups of many runs).  A run table is an array of
 // batch_arg_bytes<T>() records written by pack_batch_arg; work lists hold (run, local block).
@@ -115,7 +115,8 @@ template <typename T>
 hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, bool publish,
                               bool at, int mode, hipStream_t stream);
 template <typename T>
-hipError_t launch_at_sums_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream);
+hipError_t launch_at_sums_batch(const void* runs, const uint2* work, int64_t nblk, const double* cs,
+                                hipStream_t stream);
 int64_t view_blocks(const Geom& g);  // 256-point blocks of k_at_sums for one run
 constexpr int kModeStepH = 0, kModeRhsH = 1, kModePublishH = 2;
 

@@ -171,7 +171,7 @@ StageArgs<T> chunk_args(at_sim* s, int bstep, int st, double* tot_override) {
   a.delays = s->d_sched + (size_t)n * s->g.ntiles * 6;
   a.step = n;
   a.step_mod_r = (int)(n % s->g.R);
-  a.cstage = (T)kRkC[st];
+  a.gv = a.gv_out + (size_t)st * s->g.ring_slot;
   a.rk_a = (T)kRkA[st];
   a.rk_b = (T)kRkB[st];
   a.publish = st == 0;
@@ -238,8 +238,8 @@ hipError_t enqueue_chunk(at_batch* b, const ChunkPlan& p, hipStream_t st) {
     for (int stg = 0; stg < 3; ++stg) {
       const void* tab = b->d_buf + p.off_args[0] + (size_t)(bs * 3 + stg) * M * p.argb;
       const void* tabd = b->d_buf + p.off_args[1] + (size_t)(bs * 3 + stg) * M * p.argb;
-      if (p.views && p.nvw > 0) {
-        hipError_t e = launch_at_sums_batch<T>(tab, vw, p.nvw, st);
+      if (stg == 0 && p.views && p.nvw > 0) {  // the AT sums of all three stages of the step
+        hipError_t e = launch_at_sums_batch<T>(tab, vw, p.nvw, kRkC, st);
         if (e != hipSuccess) return e;
       }
       // runs that read delayed levels at this step run the AT instantiation (in its own launch

@@ -51,7 +51,7 @@ struct FArgs {
   int gbx, gby;  // workgroups along x and y (a batched launch decodes its local block with them)
   int views;     // batched AT sums: does this run read delayed levels at this stage
   T i12x, i12y, i12z, gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
-  T cstage, rk_a, rk_b, dt;
+  T rk_a, rk_b, dt;
   double vol;
 };
 
@@ -928,7 +928,6 @@ FArgs<T> pack(const StageArgs<T>& s, int zchunk) {
   a.mu_ref = s.cf.mu_ref;
   a.inv_tref = s.cf.inv_tref;
   a.mu_exp = s.cf.mu_exp;
-  a.cstage = s.cstage;
   a.rk_a = s.rk_a;
   a.rk_b = s.rk_b;
   a.dt = s.dt;
@@ -990,18 +989,22 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
   }
 }
 
-// AT sums of one stage, per reader (Sec. 2.1, Eq. at; Appendix B, (1,4) rows).  A point on face
+// AT sums of the three stages of a step, per reader (Sec. 2.1, Eq. at; Appendix B, (1,4) rows).  A point on face
 // layer l of PE t along d reads, across the face on its side (layers 0, 1: the lower face, read
 // from PE t-1; layers 2, 3: the upper face, from PE t+1), the stencil offsets m that leave its PE:
 // m = -2, -1 (l = 0), -2 (l = 1), +2 (l = 2), +1, +2 (l = 3).  With the reader PE's delay k >= 1 on
 // that face the value there is the extrapolation w_0 v^{n-k} + w_1 v^{n-k-1} + w_2 v^{n-k-2},
 // w from kappa = k + c_s (the Appendix B weights at c_s = 0); the kernel stores, for each of the 9
 // ring components, sum_m a_m (extrapolated value at X + m) at the reader's own ring offset, with
-// a = (1, -8, 8, -1) the stencil numerators.  One thread serves the two readers of a face (layers
-// 0, 1 or 2, 3), which share their delay and the source points across it (each extrapolated
-// once).  Readers whose face has k = 0 are not written.
+// a = (1, -8, 8, -1) the stencil numerators.  The delays and levels are those of the step, the
+// same for its three stages, which differ only in c_s: one launch per step reads the levels once
+// and writes the sums of stage s into the s-th of three consecutive slot-sized regions of gv.
+// One thread serves the two readers of a face (layers 0, 1 or 2, 3), which share their delay and
+// the source points across it (each extrapolated once).  Readers whose face has k = 0 are not
+// written.
 template <typename T>
-__device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid) {
+__device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid,
+                                             const T c0, const T c1, const T c2) {
   const uint32_t h0 = a.slab0 / 2, h1 = a.slab1 / 2, h2 = a.slab2 / 2;
   if (tid >= h0 + h1 + h2) return;
   int d, x, y, z, jp;
@@ -1049,10 +1052,14 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
   const int tn = lower ? (t == 0 ? pd - 1 : t - 1) : (t == pd - 1 ? 0 : t + 1);
   // sources: lower face: layers 2, 3 of PE tn; upper face: layers 0, 1 of PE tn
   const int sl = lower ? 2 : 0;
-  const T kap = T(k) + a.cstage;
-  const T w0 = (kap + T(1)) * (kap + T(2)) * T(0.5);
-  const T w1 = -kap * (kap + T(2));
-  const T w2 = kap * (kap + T(1)) * T(0.5);
+  T w[3][3];
+#pragma unroll
+  for (int st = 0; st < 3; ++st) {
+    const T kap = T(k) + (st == 0 ? c0 : st == 1 ? c1 : c2);
+    w[st][0] = (kap + T(1)) * (kap + T(2)) * T(0.5);
+    w[st][1] = -kap * (kap + T(2));
+    w[st][2] = kap * (kap + T(1)) * T(0.5);
+  }
   int s0 = a.step_mod_r - k;
   s0 += s0 < 0 ? a.R : 0;
   const int s1 = s0 == 0 ? a.R - 1 : s0 - 1;
@@ -1068,45 +1075,51 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
 #pragma unroll
   for (int c = 0; c < kNRing; ++c) {
     const uint32_t oa = srcA + (uint32_t)c * ss, ob = srcB + (uint32_t)c * ss;
-    const T va = w0 * r0[oa] + w1 * r1[oa] + w2 * r2[oa];
-    const T vb = w0 * r0[ob] + w1 * r1[ob] + w2 * r2[ob];
-    // lower face: reader 0 = 1 va - 8 vb (offsets -2, -1), reader 1 = 1 vb (offset -2);
-    // upper face: reader 2 = -1 va (offset +2), reader 3 = 8 va - 1 vb (offsets +1, +2)
-    const T v0 = lower ? va - T(8) * vb : -va;
-    const T v1 = lower ? vb : T(8) * va - vb;
-    gv[dst + (uint32_t)c * ss] = v0;
-    gv[dst + jstride + (uint32_t)c * ss] = v1;
+    const T a0 = r0[oa], a1 = r1[oa], a2 = r2[oa], b0 = r0[ob], b1 = r1[ob], b2 = r2[ob];
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+      const T va = w[st][0] * a0 + w[st][1] * a1 + w[st][2] * a2;
+      const T vb = w[st][0] * b0 + w[st][1] * b1 + w[st][2] * b2;
+      // lower face: reader 0 = 1 va - 8 vb (offsets -2, -1), reader 1 = 1 vb (offset -2);
+      // upper face: reader 2 = -1 va (offset +2), reader 3 = 8 va - 1 vb (offsets +1, +2)
+      const T v0 = lower ? va - T(8) * vb : -va;
+      const T v1 = lower ? vb : T(8) * va - vb;
+      T* g = gv + (uint32_t)st * a.rslot;
+      g[dst + (uint32_t)c * ss] = v0;
+      g[dst + jstride + (uint32_t)c * ss] = v1;
+    }
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_at_sums(FArgs<T> a, T* __restrict__ gv) {
-  at_sums_body<T>(a, gv, blockIdx.x * 256u + threadIdx.x);
+__global__ __launch_bounds__(256) void k_at_sums(FArgs<T> a, T* __restrict__ gv, T c0, T c1, T c2) {
+  at_sums_body<T>(a, gv, blockIdx.x * 256u + threadIdx.x, c0, c1, c2);
 }
 
-// Batched views: work[b] = (run, local block of 256 face-layer points); runs that read no
-// delayed level at this stage leave at once.
+// Batched sums: work[b] = (run, local block of 256 reader pairs); runs that read no delayed level
+// at this step leave at once.  The run table is that of the step's first stage, whose gv is the
+// base of the three regions.
 template <typename T>
 __global__ __launch_bounds__(256) void k_at_sums_batch(const FArgs<T>* __restrict__ runs,
-                                                           const uint2* __restrict__ work) {
+                                                           const uint2* __restrict__ work, T c0, T c1, T c2) {
   const uint2 w = work[blockIdx.x];
   const FArgs<T> a = runs[w.x];
   if (!a.views) return;
-  at_sums_body<T>(a, const_cast<T*>(a.gv), w.y * 256u + threadIdx.x);
+  at_sums_body<T>(a, const_cast<T*>(a.gv), w.y * 256u + threadIdx.x, c0, c1, c2);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_at_sums(const StageArgs<T>& a, hipStream_t stream) {
+hipError_t launch_at_sums(const StageArgs<T>& a, const double* cs, hipStream_t stream) {
   const Geom& g = a.g;
   const int64_t total = (g.slab[0] + g.slab[1] + g.slab[2]) / 2;  // reader pairs
   hipLaunchKernelGGL(k_at_sums<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
-                     pack<T>(a, 4), a.gv_out);
+                     pack<T>(a, 4), a.gv_out, (T)cs[0], (T)cs[1], (T)cs[2]);
   return hipGetLastError();
 }
-template hipError_t launch_at_sums<double>(const StageArgs<double>&, hipStream_t);
-template hipError_t launch_at_sums<float>(const StageArgs<float>&, hipStream_t);
+template hipError_t launch_at_sums<double>(const StageArgs<double>&, const double*, hipStream_t);
+template hipError_t launch_at_sums<float>(const StageArgs<float>&, const double*, hipStream_t);
 
 int64_t fused_blocks(const Geom& g, int tile, int zchunk) {
   const int bx = tile_bx(tile), by = tile_by(tile);
@@ -1210,10 +1223,11 @@ hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk,
 }
 
 template <typename T>
-hipError_t launch_at_sums_batch(const void* runs, const uint2* work, int64_t nblk, hipStream_t stream) {
+hipError_t launch_at_sums_batch(const void* runs, const uint2* work, int64_t nblk, const double* cs,
+                                hipStream_t stream) {
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_at_sums_batch<T>, dim3((unsigned)nblk), dim3(256), 0, stream, (const FArgs<T>*)runs,
-                     work);
+                     work, (T)cs[0], (T)cs[1], (T)cs[2]);
   return hipGetLastError();
 }
 
@@ -1223,7 +1237,7 @@ template void pack_batch_arg<float>(const StageArgs<float>&, int, int, int, void
 template void pack_batch_arg<double>(const StageArgs<double>&, int, int, int, void*);
 template hipError_t launch_fused_batch<float>(const void*, const uint2*, int64_t, int, bool, bool, bool, int, hipStream_t);
 template hipError_t launch_fused_batch<double>(const void*, const uint2*, int64_t, int, bool, bool, bool, int, hipStream_t);
-template hipError_t launch_at_sums_batch<float>(const void*, const uint2*, int64_t, hipStream_t);
-template hipError_t launch_at_sums_batch<double>(const void*, const uint2*, int64_t, hipStream_t);
+template hipError_t launch_at_sums_batch<float>(const void*, const uint2*, int64_t, const double*, hipStream_t);
+template hipError_t launch_at_sums_batch<double>(const void*, const uint2*, int64_t, const double*, hipStream_t);
 
 }  // namespace atns

@@ -51,10 +51,10 @@ def test_workspace_bytes_formula(lib):
     assert b64 > 0 and b32 > 0 and b32 < b64
     N = 32 ** 3
     # two state buffers, the RK register, the ring of 6 levels x 9 components on the face layers
-    # and one more level-sized buffer of AT face views: lower bound in FP64; the scratch beyond it
-    # (reduction partials, tables) is small
+    # and three more level-sized buffers of AT sums (one per stage of a step): lower bound in FP64;
+    # the scratch beyond it (reduction partials, tables) is small
     phi = 4 * (1 / 16 + 1 / 16 + 1 / 32)
-    ring = (6 + 1) * 9 * phi * N
+    ring = (6 + 3) * 9 * phi * N
     need = 8 * (5 + 5 + 5) * N + 8 * ring
     assert need <= b64 <= 1.1 * need
 

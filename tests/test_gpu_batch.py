@@ -192,7 +192,8 @@ def test_autotune_keeps_state_and_uses_cache(tmp_path):
         b.add(s)
     ms = b.autotune(cache, reps=2)  # at step 0, like the second batch below (same cache key)
     tile, zc = b.get_tuning()
-    say(f"  chose tile {tile} zchunk {zc}: {ms:.3f} ms per stage")
+    shapes = b.get_stage_tuning()
+    say(f"  chose shapes {shapes}: {ms:.3f} ms per stage")
     assert ms > 0 and cache.exists() and cache.read_text().count("\n") == 1
     b.step(3)
     b.autotune(None, reps=1)  # trial stages between steps leave every member's state untouched
@@ -210,7 +211,7 @@ def test_autotune_keeps_state_and_uses_cache(tmp_path):
     b2.set_tuning(5, 8)
     assert b2.autotune(cache, reps=2) == pytest.approx(ms)
     assert b2.get_tuning() == (tile, zc)
-    assert b2.get_stage_tuning() == b.get_stage_tuning()
+    assert b2.get_stage_tuning() == shapes
     assert cache.read_text().count("\n") == 1
 
 
