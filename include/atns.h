@@ -101,9 +101,10 @@ ATNS_API const char* at_version(void);
 ATNS_API const char* at_last_error(void);
 
 /* Bytes of device workspace at_create needs for `cfg` (0 if cfg is invalid).  Holds two conserved
- * state buffers (a stage reads one and writes the other), the RK register, and the ring of
+ * state buffers (a stage reads one and writes the other), the RK register, the ring of
  * published face layers: (max_delay + 3) levels x 9 components (u, v, w, T and the face-normal flux of the five
- * conserved variables) x 4 (1/ex + 1/ey + 1/ez) N^3 points. */
+ * conserved variables) x 4 (1/ex + 1/ey + 1/ez) N^3 points, and three level-sized buffers of the
+ * AT sums of the face-layer readers (one per RK stage of a step), plus small reduction scratch. */
 ATNS_API size_t at_workspace_bytes(const at_config* cfg);
 
 /* Create a simulation handle.  dev_workspace: device memory of at least at_workspace_bytes(cfg)

@@ -11,11 +11,16 @@
 // One thread per column of the tile and of its 2-wide x and y halos (wave-uniform roles, see
 // Tile), each keeping a five-plane register window of its column's primitives for the z
 // derivatives and writing the current plane to LDS for the x and y derivatives; the remaining
-// halo points the x / y derivatives need are loaded one plane ahead by the first threads.  The
+// halo points the x / y derivatives need are loaded one plane ahead by the first waves.  The
 // tile computes all three fluxes, the halo rows F_y and the halo columns F_x; F_x and F_y reach
 // the tile through LDS, F_z stays in the owning thread and is scattered into a five-plane register
 // accumulator, so the z divergence needs no LDS.  The state is read from one buffer and written
 // to the other, so halo reads never see updated values.
+//
+// Fetches for a later plane (the state of plane z + 4, the plane-only halo points of z + 2, the AT
+// sums of z + 1) are issued after the last use of the registers they refill and on every lane of
+// the waves that use them: loads complete in order, and a refill copied into place, or one whose
+// use the wait analysis cannot pair with it, would make the wave wait for it before the barrier.
 //
 // Indexing is 32-bit (element offsets below 2^32, checked by the host) and every per-column
 // quantity is computed once; per-plane quantities are uniform across the workgroup.
@@ -153,7 +158,7 @@ __device__ __forceinline__ void prim_of(const T q[5], T inv_cv, T& r, T& u, T& v
 //   [NOWN, NOWN + NY2)   the 2 + 2 rows of y-halo columns (flux F_y only)
 //   [.., NCOL)           the 2 + 2 columns of x-halo columns (flux F_x only)
 // and, per plane, NXTRA plane-only points (x halo 3-4, y halo 3-4, the 16 corners) that feed the
-// x / y derivatives of the halo columns, loaded one plane ahead by the first NXTRA threads.
+// x / y derivatives of the halo columns, held by the first NXTRA threads (fetched one plane ahead).
 template <int BX, int BY>
 struct Tile {
   static constexpr int NOWN = BX * BY;
@@ -456,9 +461,9 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
 
   // Delays of this column's PE, cached per z-PE: the x / y face delays its stencils can cross (0
   // away from those faces) with the masked x / y stencil coefficients, and both z-face delays; for
-  // plane zc (gradients) and, one plane behind, zc - 1 (divergence).  The AT sums the column reads
-  // are loaded one iteration ahead (vx, vy: gradients of plane zc; vfx, vfy: divergence of plane
-  // zc - 1), so that their latency overlaps a whole plane of work.
+  // plane zc (gradients) and, one plane behind, zc - 1 (divergence).  The gradient AT sums are
+  // fetched one iteration ahead (vx, vy: plane zc), the divergence ones (vfx, vfy: plane zc - 1)
+  // right after the gradients, so that the fluxes hide them.
   int tz_c = -1, kcx = 0, kcy = 0, kzl = 0, kzh = 0, kcx_d = 0, kcy_d = 0;
   T bx[4], by[4], bxd[4], byd[4], vx[4], vy[4];
 #pragma unroll
