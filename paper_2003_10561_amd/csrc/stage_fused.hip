@@ -394,7 +394,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       }
   }
 
-  T raw[5], xraw[5];
+  // (zero where a lane never fetches them: every path then reads defined values, see below)
+  T raw[5], xraw[5] = {}, fq[5] = {}, fd[5] = {};
   T acc[5][kNQ];
   if (role == 0) {
 #pragma unroll
@@ -517,7 +518,6 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     const int zf = zc - 2;
     const bool fin = valid && zf >= z0 && zf < z1 && mode != kModePublish;
     const uint32_t fi = (uint32_t)pmod(zf, nz) * plane + col;
-    T fq[5], fd[5];
 
     // fluxes of this column at plane zc: the tile computes all three (F_z also just outside the
     // chunk, for the z divergence), the halo rows F_y and the halo columns F_x
