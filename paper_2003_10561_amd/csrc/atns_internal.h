@@ -74,6 +74,8 @@ struct StageArgs {
   T rk_a, rk_b, dt;
   int publish;        // stage 1: write level n into the ring
   int store_dq;       // 0 in the last stage (the register is not read again)
+  int at_ghost;       // the delayed stages of this step run on tiles aligned with the PEs: the x / y
+                      // entries of gv are extrapolated halo values, not per-reader sums
   double* tot_part;   // [nblk][5] FP64 running sums of B_s * sum(dQ) * h^3
   double vol;         // h_x h_y h_z
   ForceArgs<T> force;
@@ -96,6 +98,9 @@ __host__ __device__ constexpr TileShape tile_shape(int t) {
 }
 __host__ __device__ inline int tile_bx(int t) { return tile_shape(t).bx; }
 __host__ __device__ inline int tile_by(int t) { return tile_shape(t).by; }
+// Every workgroup tile of this shape lies inside one PE along x and y (PE edges multiples of the
+// tile's): delayed stages then place the extrapolated values in the tile halo.
+inline bool tile_aligned(const Geom& g, int t) { return g.e[0] % tile_bx(t) == 0 && g.e[1] % tile_by(t) == 0; }
 int64_t fused_blocks(const Geom& g, int tile, int zchunk);
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per compute unit on gfx950
 size_t fused_lds_bytes(int tile, size_t word, bool forced);
@@ -111,9 +116,12 @@ template <typename T>
 size_t batch_arg_bytes();
 template <typename T>
 void pack_batch_arg(const StageArgs<T>& s, int tile, int zchunk, int views, void* dst);
+// at: 0 for the plain instantiation; else which AT instantiations to launch over the work list,
+// kAtMasked (runs without at_ghost) and / or kAtGhost (runs with it)
+constexpr int kAtMasked = 1, kAtGhost = 2;
 template <typename T>
 hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, bool publish,
-                              bool at, int mode, hipStream_t stream);
+                              int at, int mode, hipStream_t stream);
 template <typename T>
 hipError_t launch_at_sums_batch(const void* runs, const uint2* work, int64_t nblk, const double* cs,
                                 hipStream_t stream);

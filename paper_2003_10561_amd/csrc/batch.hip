@@ -86,6 +86,7 @@ struct ChunkPlan {
   int K = 0;
   int64_t nsw[2] = {0, 0}, nvw = 0;  // stage work-list entries of either launch shape; view entries
   bool views = false;                 // launch the batched AT sums and AT stages at every stage
+  int at_kinds = 0;                   // AT instantiations its delayed runs need (kAtMasked, kAtGhost)
   std::vector<int> forced;   // indices of forced runs
 
   size_t off_sw[2] = {0, 0}, off_vw = 0, off_fh = 0, off_args[2] = {0, 0}, total = 0, argb = 0;
@@ -102,6 +103,7 @@ ChunkPlan plan_chunk(const at_batch* b, int K) {
     if (ever_delayed(s)) {
       p.views = true;
       p.nvw += view_blocks(s->g);
+      p.at_kinds |= tile_aligned(s->g, b->tile_d) ? kAtGhost : kAtMasked;
     }
     if (s->cfg.forcing) p.forced.push_back((int)m);
   }
@@ -210,7 +212,8 @@ void fill_chunk(at_batch* b, const ChunkPlan& p, uint8_t* h) {
     for (int st = 0; st < 3; ++st)
       for (size_t m = 0; m < M; ++m) {
         at_sim* s = b->runs[m];
-        const StageArgs<T> a = chunk_args<T>(s, bs, st, nullptr);
+        StageArgs<T> a = chunk_args<T>(s, bs, st, nullptr);
+        a.at_ghost = tile_aligned(s->g, b->tile_d) ? 1 : 0;  // the batch's delayed-stage shape
         const int views = s->step_delayed[(size_t)(s->step + bs)] ? 1 : 0;
         for (int kd = 0; kd < nk; ++kd)
           pack_batch_arg<T>(a, kind_tile(b, kd), run_zchunk(b, s, kd), views,
@@ -246,10 +249,10 @@ hipError_t enqueue_chunk(at_batch* b, const ChunkPlan& p, hipStream_t st) {
       // shape), the others the plain one (each leaves the other's launch at once); both are
       // launched at every stage of a batch with any delayed schedule, so that a chunk's graph
       // depends only on membership, launch shapes and length
-      hipError_t e = launch_fused_batch<T>(tab, sw, p.nsw[0], b->tile, forced, stg == 0, false, kModeStepH, st);
+      hipError_t e = launch_fused_batch<T>(tab, sw, p.nsw[0], b->tile, forced, stg == 0, 0, kModeStepH, st);
       if (e != hipSuccess) return e;
       if (p.views) {
-        e = launch_fused_batch<T>(tabd, swd, p.nsw[1], b->tile_d, forced, stg == 0, true, kModeStepH, st);
+        e = launch_fused_batch<T>(tabd, swd, p.nsw[1], b->tile_d, forced, stg == 0, p.at_kinds, kModeStepH, st);
         if (e != hipSuccess) return e;
       }
     }
@@ -261,6 +264,7 @@ std::vector<uint64_t> chunk_signature(const at_batch* b, const ChunkPlan& p) {
   std::vector<uint64_t> sg = {(uint64_t)b->tile, (uint64_t)b->zchunk, (uint64_t)b->tile_d, (uint64_t)b->zchunk_d,
                               (uint64_t)p.K, (uint64_t)b->precision, (uint64_t)(uintptr_t)b->d_buf,
                               (uint64_t)p.nsw[0], (uint64_t)p.nsw[1], (uint64_t)p.nvw, (uint64_t)p.views,
+                              (uint64_t)p.at_kinds,
                               (uint64_t)p.off_args[0], (uint64_t)p.off_args[1], (uint64_t)p.off_fh,
                               (uint64_t)p.off_vw};
   for (const at_sim* s : b->runs) {
@@ -342,7 +346,7 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, doubl
   uint2* sw = (uint2*)(h + p.off_sw[0]);
   int64_t is = 0;
   size_t tot_off = 0;
-  bool any_at = false;
+  int at_kinds = 0;
   const size_t M = b->runs.size();
   for (size_t m = 0; m < M; ++m) {
     at_sim* s = b->runs[m];
@@ -351,6 +355,7 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, doubl
     for (int64_t k = 0; k < nb; ++k) sw[is++] = make_uint2((unsigned)m, (unsigned)k);
     StageArgs<T> a = chunk_args<T>(s, 0, 0, b->d_trial_tot + tot_off);
     a.publish = 0;
+    a.at_ghost = tile_aligned(s->g, tile) ? 1 : 0;
     if (s->cfg.forcing) a.force.table = (T*)(s->ws + s->L.force_table);
     tot_off += (size_t)s->L.ntot * kNQ;
     int views = 0;
@@ -359,7 +364,7 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, doubl
       a.delays = s->d_sched + (size_t)nd * s->g.ntiles * 6;
       a.step_mod_r = (int)(nd % s->g.R);
       views = 1;
-      any_at = true;
+      at_kinds |= a.at_ghost ? kAtGhost : kAtMasked;
     }
     pack_batch_arg<T>(a, tile, zc, views, h + p.off_args[0] + m * p.argb);
   }
@@ -367,11 +372,10 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, doubl
   const bool forced = !p.forced.empty();
   const void* tab = b->d_buf + p.off_args[0];
   const uint2* dsw = (const uint2*)(b->d_buf + p.off_sw[0]);
-  const bool at = any_at;
   auto trial = [&]() -> hipError_t {
-    hipError_t e = launch_fused_batch<T>(tab, dsw, p.nsw[0], tile, forced, false, false, kModeStepH, b->stream);
-    if (e == hipSuccess && at)
-      e = launch_fused_batch<T>(tab, dsw, p.nsw[0], tile, forced, false, true, kModeStepH, b->stream);
+    hipError_t e = launch_fused_batch<T>(tab, dsw, p.nsw[0], tile, forced, false, 0, kModeStepH, b->stream);
+    if (e == hipSuccess && at_kinds)
+      e = launch_fused_batch<T>(tab, dsw, p.nsw[0], tile, forced, false, at_kinds, kModeStepH, b->stream);
     return e;
   };
   HIP_TRY(trial());

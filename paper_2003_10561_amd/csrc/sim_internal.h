@@ -105,6 +105,7 @@ StageArgs<T> base_args(at_sim* s) {
   a.ring = (T*)(s->ws + s->L.ring);
   a.gv_out = (T*)(s->ws + s->L.gv);
   a.gv = a.gv_out;
+  a.at_ghost = tile_aligned(s->g, s->tile_d) ? 1 : 0;
   a.tot_part = (double*)(s->ws + s->L.tot_part);
   a.vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
   a.dt = (T)s->cfg.dt;

@@ -55,6 +55,7 @@ struct FArgs {
   int R, step_mod_r, npair, zchunk, publish, store_dq;
   int gbx, gby;  // workgroups along x and y (a batched launch decodes its local block with them)
   int views;     // batched AT sums: does this run read delayed levels at this stage
+  int at_ghost;  // x / y AT entries are extrapolated halo values (delayed stages on aligned tiles)
   T i12x, i12y, i12z, gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
   T rk_a, rk_b, dt;
   double vol;
@@ -121,6 +122,40 @@ __device__ __forceinline__ constexpr T stencil_a(int mi) {
 // Bit mi set: offset m(mi) of a point at local index l in a PE of edge e >= 4 crosses a PE face.
 __device__ __forceinline__ int crossing_mask(int l, int e) {
   return (l == 0 ? 0x3 : l == 1 ? 0x1 : 0) | (l == e - 1 ? 0xC : l == e - 2 ? 0x8 : 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c) { return fma(a, b, c); }
+template <>
+__device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The (1,4) stencil numerator in one fixed association, (v(-2) - 8 v(-1)) + (8 v(+1) - v(+2)), in
+// every instantiation.  An AT derivative is this expression with the points across a delayed face
+// replaced by their extrapolated values (Sec. 2.1, Eq. at); the two ways of evaluating it round
+// identically:
+//  * ghost points in the operands (aligned tiles: the halo holds the extrapolated values), or
+//  * the reader's AT sum V in place of the half it covers (masked_num): V is that half with the
+//    ghost operands, formed by the AT-sum kernel (or ghost_sum) with the same operations.
+template <typename T>
+__device__ __forceinline__ T central_num(T m2, T m1, T p1, T p2) {
+  return fmaT(T(-8), m1, m2) + fmaT(T(8), p1, -p2);
+}
+
+// cm = crossing_mask of the reader (nonzero only on one side for e >= 4): layer 0 takes L = V,
+// layer 1 L = V - 8 v(-1) (V = v(-1)), layer e-2 R = 8 v(+1) + V (V = -v(+2)), layer e-1 R = V.
+template <typename T>
+__device__ __forceinline__ T masked_num(T m2, T m1, T p1, T p2, int cm, T V) {
+  const T L = (cm & 2) ? V : fmaT(T(-8), m1, (cm & 1) ? V : m2);
+  const T R = (cm & 4) ? V : fmaT(T(8), p1, (cm & 8) ? V : -p2);
+  return L + R;
+}
+
+// AT sum of a reader from the two extrapolated values g0, g1 stored at the slots of its face's
+// readers (lower face: g0 at layer -2, g1 at -1; upper: g0 at e, g1 at e+1).
+template <typename T>
+__device__ __forceinline__ T at_sum_of(bool lower, bool outer, T g0, T g1) {
+  // lower: layer 0 (outer) g0 - 8 g1, layer 1 g1; upper: layer e-2 -g0, layer e-1 (outer) 8 g0 - g1
+  return lower ? (outer ? fmaT(T(-8), g1, g0) : g1) : (outer ? fmaT(T(8), g0, -g1) : -g0);
 }
 
 // Zero, produced by an instruction that reads v.  Added to the address of a fetch that refills the
@@ -276,10 +311,16 @@ struct ZWin<T, NCOL, false> {
 // One workgroup of a stage: the BX x BY column tile (bkx, bky) and z chunk bkz of run `a`; `blk`
 // is its slot among the run's workgroups for the FP64 totals.  PUB: this stage publishes the face
 // layers (stage 1 of a step, or a history level); AT: some face of the run is delayed at this
-// stage.  Each is compiled out of the stages that do not need it.
-template <typename T, int BX, int BY, bool PUB, bool AT>
+// stage.  Each is compiled out of the stages that do not need it.  SUB (with AT, tiles aligned with
+// the PEs along x and y): the halo columns within 2 of a delayed face of the tile's PE hold the
+// extrapolated values (primitives in the LDS plane, the face-normal flux in the flux plane), so the
+// tile's columns evaluate the central form; halo columns that compute (their own PE's face delayed,
+// the tile's not) form their AT sums from the extrapolated values when they need them.  Without SUB
+// every column whose face is delayed uses masked operands and AT sums fetched a plane ahead.
+template <typename T, int BX, int BY, bool PUB, bool AT, bool SUB>
 __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, const int bkx, const int bky,
                                            const int bkz, const uint32_t blk) {
+  constexpr bool kMask = AT && !SUB, kSub = AT && SUB;
   using TL = Tile<BX, BY>;
   constexpr int LW = TL::LW, LH = TL::LH;
   __shared__ T s_pr[2][4][LH][LW];       // u, v, w, T of a plane (two buffers: planes alternate)
@@ -350,9 +391,30 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   const uint32_t zsx = (uint32_t)ny * (uint32_t)(4 * a.px), zsy = (uint32_t)(4 * a.py) * (uint32_t)nx;
   const uint32_t opx = (uint32_t)gy * (uint32_t)(4 * a.px) + (uint32_t)jx;    // + z zsx
   const uint32_t opy = a.rdir1 + (uint32_t)jy * (uint32_t)nx + (uint32_t)gx;  // + z zsy
-  // AT by masked stencil coefficients: where this column's PE face is delayed (k >= 1) the
-  // offsets that cross it get coefficient 0 and the reader adds its precomputed AT sum
+  // AT by masked operands: where this column's PE face is delayed (k >= 1) the reader's AT sum
+  // replaces the half of the stencil that crosses it (masked_num)
   const int cxm = crossing_mask(lxe, a.ex), cym = crossing_mask(lye, a.ey);
+  // SUB: the tile's PE (ttx, tty); a halo column on the first two layers across one of its faces
+  // is that face's ghost (gside 0..3 = lower x, upper x, lower y, upper y; -1 none) and finds the
+  // extrapolated values at gofs (+ z term gzs, component stride gss): the slots of that face's
+  // tile-PE readers, layer -2, -1 (or e, e+1) at readers 0, 1 (or 2, 3)
+  const int ttx = x0 / a.ex, tty = y0 / a.ey;
+  int gside = -1;
+  uint32_t gofs = 0;
+  if (kSub && role == 2) {
+    const int c = (tid - TL::NOWN - TL::NY2) / BY;
+    if (c < 2 ? x0 == ttx * a.ex : x0 + BX == (ttx + 1) * a.ex) {
+      gside = c < 2 ? 0 : 1;
+      gofs = (uint32_t)gy * (uint32_t)(4 * a.px) + (uint32_t)(4 * ttx + c);
+    }
+  } else if (kSub && role == 1) {
+    const int r = (tid - TL::NOWN) / BX;
+    if (r < 2 ? y0 == tty * a.ey : y0 + BY == (tty + 1) * a.ey) {
+      gside = r < 2 ? 2 : 3;
+      gofs = a.rdir1 + (uint32_t)(4 * tty + r) * (uint32_t)nx + (uint32_t)gx;
+    }
+  }
+  const uint32_t gzs = role == 2 ? zsx : zsy, gss = role == 2 ? a.slab0 : a.slab1;
   const T* __restrict__ qin = a.q;
   const T inv_cv = a.inv_cv;
 
@@ -429,6 +491,52 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
 #pragma unroll
     for (int c = 0; c < 5; ++c) xraw[c] = qin[c * N + i1];
   }
+  // Delays of this column's PE, cached per z-PE: the x / y face delays its stencils can cross (0
+  // away from those faces, and for the tile's columns under SUB), for plane zc (gradients) and,
+  // one plane behind, zc - 1 (divergence); the z-face delays in one word kz (bytes: its lower and
+  // upper face, the upper face of the z-PE below and the lower face of the one above); under SUB
+  // also gk, the delay of the tile-PE face this column is a ghost of (0: none, or not delayed).
+  // Without SUB the gradient AT sums are fetched one iteration ahead (vx, vy: plane zc), the
+  // divergence ones (vfx, vfy: plane zc - 1) right after the gradients, so that the fluxes hide them.
+  int tz_c = -1, kcx = 0, kcy = 0, kz = 0, kcx_d = 0, kcy_d = 0, gk = 0;
+  T vx[4], vy[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) vx[c] = vy[c] = T(0);
+  auto plane_delays = [&](int zpl) {
+    if (!AT) return;
+    const int gzp = pmod(zpl, nz), tzp = gzp / a.ez;
+    if (tzp != tz_c) {  // uniform: a new z-PE
+      tz_c = tzp;
+      if (column) {
+        const int8_t* kf = a.delays + ((tzp * a.py + ty) * a.px + tx) * 6;
+        const bool own = !kSub || role != 0;
+        kcx = own && near_x ? (lxe < 2 ? kf[0] : kf[1]) : 0;
+        kcy = own && near_y ? (lye < 2 ? kf[2] : kf[3]) : 0;
+        const int pz = nz / a.ez;
+        const int tzb = tzp == 0 ? pz - 1 : tzp - 1, tza = tzp == pz - 1 ? 0 : tzp + 1;
+        const int kb = a.delays[((tzb * a.py + ty) * a.px + tx) * 6 + 5];
+        const int ka = a.delays[((tza * a.py + ty) * a.px + tx) * 6 + 4];
+        kz = (kf[4] & 0xff) | ((kf[5] & 0xff) << 8) | ((kb & 0xff) << 16) | ((ka & 0xff) << 24);
+        if (kSub) gk = gside >= 0 ? a.delays[((tzp * a.py + tty) * a.px + ttx) * 6 + gside] : 0;
+      }
+    }
+    if (kMask && __builtin_expect(kcx > 0, 0)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vx[c] = at_sum<T>(a, 0, c, (uint32_t)gzp * zsx + opx);
+    }
+    if (kMask && __builtin_expect(kcy > 0, 0)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vy[c] = at_sum<T>(a, 1, c, (uint32_t)gzp * zsy + opy);
+    }
+  };
+  // SUB: the extrapolated u, v, w, T of plane zpl at this ghost column into an LDS plane buffer
+  auto put_ghost_prims = [&](T (*dst)[LH][LW], int zpl) {
+    const uint32_t o = gofs + (uint32_t)pmod(zpl, nz) * gzs;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c][py][px] = a.gv[o + (uint32_t)c * gss];
+  };
+  if (kSub) plane_delays(z0 - 2);
+
   // window plane z0, then the LDS plane z0 - 2 (buffer parity (z + 2) & 1)
   if (column) {
     T r_, u_, v_, w_, t_;
@@ -441,10 +549,14 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       for (int c = 0; c < 5; ++c) raw[c] = qin[c * N + i];
     }
     const int b0 = z0 & 1;
-    s_pr[b0][0][py][px] = zw.get(0, 2);
-    s_pr[b0][1][py][px] = zw.get(1, 2);
-    s_pr[b0][2][py][px] = zw.get(2, 2);
-    s_pr[b0][3][py][px] = zw.get(3, 2);
+    if (kSub && gk > 0) {
+      put_ghost_prims(s_pr[b0], z0 - 2);
+    } else {
+      s_pr[b0][0][py][px] = zw.get(0, 2);
+      s_pr[b0][1][py][px] = zw.get(1, 2);
+      s_pr[b0][2][py][px] = zw.get(2, 2);
+      s_pr[b0][3][py][px] = zw.get(3, 2);
+    }
   }
   if (ex_ >= 0) {
     T xr, xu, xv, xw, xt;
@@ -460,46 +572,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   }
   __syncthreads();
 
-  // Delays of this column's PE, cached per z-PE: the x / y face delays its stencils can cross (0
-  // away from those faces) with the masked x / y stencil coefficients, and both z-face delays; for
-  // plane zc (gradients) and, one plane behind, zc - 1 (divergence).  The gradient AT sums are
-  // fetched one iteration ahead (vx, vy: plane zc), the divergence ones (vfx, vfy: plane zc - 1)
-  // right after the gradients, so that the fluxes hide them.
-  int tz_c = -1, kcx = 0, kcy = 0, kzl = 0, kzh = 0, kcx_d = 0, kcy_d = 0;
-  T bx[4], by[4], bxd[4], byd[4], vx[4], vy[4];
-#pragma unroll
-  for (int mi = 0; mi < 4; ++mi) {
-    bx[mi] = by[mi] = bxd[mi] = byd[mi] = stencil_a<T>(mi);
-    vx[mi] = vy[mi] = T(0);
-  }
-  auto plane_delays = [&](int zpl) {
-    if (!AT) return;
-    const int gzp = pmod(zpl, nz), tzp = gzp / a.ez;
-    if (tzp != tz_c) {  // uniform: a new z-PE
-      tz_c = tzp;
-      if (column) {
-        const int8_t* kf = a.delays + ((tzp * a.py + ty) * a.px + tx) * 6;
-        kcx = near_x ? (lxe < 2 ? kf[0] : kf[1]) : 0;
-        kcy = near_y ? (lye < 2 ? kf[2] : kf[3]) : 0;
-        kzl = kf[4];
-        kzh = kf[5];
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi) {
-          bx[mi] = (kcx > 0 && ((cxm >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
-          by[mi] = (kcy > 0 && ((cym >> mi) & 1)) ? T(0) : stencil_a<T>(mi);
-        }
-      }
-    }
-    if (__builtin_expect(kcx > 0, 0)) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) vx[c] = at_sum<T>(a, 0, c, (uint32_t)gzp * zsx + opx);
-    }
-    if (__builtin_expect(kcy > 0, 0)) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) vy[c] = at_sum<T>(a, 1, c, (uint32_t)gzp * zsy + opy);
-    }
-  };
-  plane_delays(z0 - 2);
+  if (!kSub) plane_delays(z0 - 2);
 
   // Iteration zc: fluxes of plane zc (LDS buffers of parity zc), x-y divergence of plane zc - 1,
   // update of plane zc - 2, then the window and LDS plane for zc + 1; one barrier per plane.
@@ -508,7 +581,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     const int gz = pmod(zc, nz);
     const int tz = gz / a.ez;
     const int lze = gz - tz * a.ez;
-    const int kcz = !AT ? 0 : lze < 2 ? kzl : (lze >= a.ez - 2 ? kzh : 0);
+    const int kcz = !AT ? 0 : lze < 2 ? (kz & 0xff) : (lze >= a.ez - 2 ? (kz >> 8) & 0xff : 0);
     T vfx[kNQ], vfy[kNQ];
 #pragma unroll
     for (int c = 0; c < kNQ; ++c) vfx[c] = vfy[c] = T(0);
@@ -525,7 +598,23 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     const bool need_fx = (role == 0 || role == 2) && zin && mode != kModePublish;
     const bool need_fy = (role == 0 || role == 1) && zin && mode != kModePublish;
     const bool need_fz = valid && mode != kModePublish;
-    if (need_fx || need_fy || need_fz || pub) {
+    if (kSub && gk > 0) {
+      // a ghost of a delayed tile-PE face: its flux-plane entry is the extrapolated face-normal
+      // flux (it computes nothing)
+      if (zin && mode != kModePublish) {
+        const uint32_t o = gofs + (uint32_t)gz * gzs;
+        T F[kNQ];
+#pragma unroll
+        for (int c = 0; c < kNQ; ++c) F[c] = a.gv[o + (uint32_t)(4 + c) * gss];
+        if (role == 2) {
+#pragma unroll
+          for (int c = 0; c < kNQ; ++c) s_fx[bc][c][py - 4][px - 2] = F[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < kNQ; ++c) s_fy[bc][c][py - 2][px - 4] = F[c];
+        }
+      }
+    } else if (need_fx || need_fy || need_fz || pub) {
       T G[kNGrad];
       // derivatives of u, v, w, T: x and y from the LDS plane, z from the window.  Where a stencil
       // crosses a delayed face the points across carry coefficient 0 and the reader's AT sum
@@ -534,26 +623,54 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       // the masked forms only in waves that hold a reader of a delayed face (wave-uniform test)
       const bool wx = AT && __builtin_amdgcn_ballot_w64(kcx > 0) != 0;
       const bool wy = AT && __builtin_amdgcn_ballot_w64(kcy > 0) != 0;
+      T sx[4], sy[4];  // the AT sums of this plane's readers: fetched ahead, or (SUB) formed here
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sx[c] = kMask ? vx[c] : T(0);
+        sy[c] = kMask ? vy[c] : T(0);
+      }
+      if (kSub && wx && kcx > 0) {
+        // a halo column next to its own delayed x face: its AT sums from the two extrapolated
+        // values at its face's reader slots
+        const uint32_t o = (uint32_t)gz * zsx + opx - (uint32_t)(lxe < 2 ? lxe : lxe - a.ex + 2);
+        const bool lo = lxe < 2, outer = lxe == 0 || lxe == a.ex - 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sx[c] = at_sum_of<T>(lo, outer, a.gv[o + (uint32_t)c * a.slab0],
+                                                          a.gv[o + 1 + (uint32_t)c * a.slab0]);
+      }
+      if (kSub && wy && kcy > 0) {
+        const uint32_t o = (uint32_t)gz * zsy + opy - (uint32_t)(lye < 2 ? lye : lye - a.ey + 2) * (uint32_t)nx;
+        const bool lo = lye < 2, outer = lye == 0 || lye == a.ey - 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sy[c] = at_sum_of<T>(lo, outer, a.gv[o + (uint32_t)c * a.slab1],
+                                                          a.gv[o + (uint32_t)nx + (uint32_t)c * a.slab1]);
+      }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const T xm2 = s_pr[bc][c][py][px - 2], xm1 = s_pr[bc][c][py][px - 1], xp1 = s_pr[bc][c][py][px + 1],
                 xp2 = s_pr[bc][c][py][px + 2];
         const T ym2 = s_pr[bc][c][py - 2][px], ym1 = s_pr[bc][c][py - 1][px], yp1 = s_pr[bc][c][py + 1][px],
                 yp2 = s_pr[bc][c][py + 2][px];
-        T dx = xm2 - T(8) * xm1 + T(8) * xp1 - xp2;
-        T dy = ym2 - T(8) * ym1 + T(8) * yp1 - yp2;
-        if (wx && kcx > 0) dx = bx[0] * xm2 + bx[1] * xm1 + bx[2] * xp1 + bx[3] * xp2 + vx[c];
-        if (wy && kcy > 0) dy = by[0] * ym2 + by[1] * ym1 + by[2] * yp1 + by[3] * yp2 + vy[c];
+        T dx = central_num(xm2, xm1, xp1, xp2);
+        T dy = central_num(ym2, ym1, yp1, yp2);
+        if (wx && kcx > 0) dx = masked_num(xm2, xm1, xp1, xp2, cxm, sx[c]);
+        if (wy && kcy > 0) dy = masked_num(ym2, ym1, yp1, yp2, cym, sy[c]);
         set_grad(G, c, 0, dx * a.i12x);
         set_grad(G, c, 1, dy * a.i12y);
         set_grad(G, c, 2, (WIN(c, 0) - T(8) * WIN(c, 1) + T(8) * WIN(c, 3) - WIN(c, 4)) * a.i12z);
       }
       if (__builtin_expect(kcz > 0, 0)) {
-        // near a delayed z face (the same for the whole plane unless the column's PEs differ)
+        // near a delayed z face (the same for the whole plane unless the column's PEs differ): the
+        // AT sums of all nine components in one round trip, the primitives' for the z derivatives
+        // and the face-normal flux's for this plane's z divergence, which takes them in place of
+        // the F_z values across the face (left out of the scatter)
         const uint32_t oz = slab_off(a, 2, gx, gy, gz);
+        T sz[kNRing];
+#pragma unroll
+        for (int c = 0; c < kNRing; ++c) sz[c] = at_sum<T>(a, 2, c, oz);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          T dz = at_sum<T>(a, 2, c, oz);
+          T dz = sz[c];
 #pragma unroll
           for (int mi = 0; mi < 4; ++mi) {
             const int m = mi < 2 ? mi - 2 : mi - 1;
@@ -562,6 +679,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
           }
           set_grad(G, c, 2, dz * a.i12z);
         }
+#pragma unroll
+        for (int c = 0; c < kNQ; ++c) acc[2][c] -= sz[4 + c] * a.i12z;
       }
       // fetched now, after the gradients, so that the gradients' wait for their AT sums (fetched in
       // the last iteration) covers no newer fetch; the fluxes hide these: the state and register of
@@ -575,12 +694,12 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
           for (int c = 0; c < 5; ++c) fd[c] = __builtin_nontemporal_load(a.dq + c * N + fi);
         }
       }
-      if (__builtin_expect(valid && kcx_d > 0, 0)) {
+      if (kMask && __builtin_expect(valid && kcx_d > 0, 0)) {
         const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsx + opx;
   #pragma unroll
         for (int c = 0; c < kNQ; ++c) vfx[c] = at_sum<T>(a, 0, 4 + c, o);
       }
-      if (__builtin_expect(valid && kcy_d > 0, 0)) {
+      if (kMask && __builtin_expect(valid && kcy_d > 0, 0)) {
         const uint32_t o = (uint32_t)pmod(zc - 1, nz) * zsy + opy;
   #pragma unroll
         for (int c = 0; c < kNQ; ++c) vfy[c] = at_sum<T>(a, 1, 4 + c, o);
@@ -669,8 +788,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         if (need_fz) {
           // scatter F_z(zc) into the receivers zc + r (RHS -= D_z F_z).  The source sits at
           // offset m = -r from receiver zc + r; a receiver in another z-PE whose face is delayed
-          // takes no contribution from it and adds its AT sum instead when it is finalized (the
-          // receiver's PE owns that decision).
+          // takes no contribution from it and has added its AT sum instead (the receiver's PE owns
+          // that decision).
           // only a source within 2 planes of its z-PE's faces (uniform) has receivers across
           const bool zface = AT && (lze < 2 || lze >= a.ez - 2);
 #pragma unroll
@@ -683,11 +802,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
             bool keep = true;
             if (zface) {
               const int l = lze - m;  // the receiver in this z-PE's local coordinates
-              if (l < 0 || l >= a.ez) {
-                const int gzp = pmod(zp, nz);
-                const int tzp = gzp / a.ez;
-                keep = a.delays[((tzp * a.py + ty) * a.px + tx) * 6 + (l < 0 ? 5 : 4)] == 0;
-              }
+              if (l < 0) keep = ((kz >> 16) & 0xff) == 0;  // in the z-PE below
+              if (l >= a.ez) keep = ((kz >> 24) & 0xff) == 0;  // in the one above
             }
             if (keep) {
 #pragma unroll
@@ -700,18 +816,18 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
 
     if (valid && zin_d && mode != kModePublish) {
       const int fxx = px - 2, fyy = py - 2;  // this point in s_fx (column) and s_fy (row)
-      const bool wx = AT && __builtin_amdgcn_ballot_w64(kcx_d > 0) != 0;
-      const bool wy = AT && __builtin_amdgcn_ballot_w64(kcy_d > 0) != 0;
+      const bool wx = kMask && __builtin_amdgcn_ballot_w64(kcx_d > 0) != 0;
+      const bool wy = kMask && __builtin_amdgcn_ballot_w64(kcy_d > 0) != 0;
 #pragma unroll
       for (int c = 0; c < kNQ; ++c) {
         const T xm2 = s_fx[bd][c][py - 4][fxx - 2], xm1 = s_fx[bd][c][py - 4][fxx - 1],
                 xp1 = s_fx[bd][c][py - 4][fxx + 1], xp2 = s_fx[bd][c][py - 4][fxx + 2];
         const T ym2 = s_fy[bd][c][fyy - 2][px - 4], ym1 = s_fy[bd][c][fyy - 1][px - 4],
                 yp1 = s_fy[bd][c][fyy + 1][px - 4], yp2 = s_fy[bd][c][fyy + 2][px - 4];
-        T dfx = xm2 - T(8) * xm1 + T(8) * xp1 - xp2;
-        T dfy = ym2 - T(8) * ym1 + T(8) * yp1 - yp2;
-        if (wx && kcx_d > 0) dfx = bxd[0] * xm2 + bxd[1] * xm1 + bxd[2] * xp1 + bxd[3] * xp2 + vfx[c];
-        if (wy && kcy_d > 0) dfy = byd[0] * ym2 + byd[1] * ym1 + byd[2] * yp1 + byd[3] * yp2 + vfy[c];
+        T dfx = central_num(xm2, xm1, xp1, xp2);
+        T dfy = central_num(ym2, ym1, yp1, yp2);
+        if (wx && kcx_d > 0) dfx = masked_num(xm2, xm1, xp1, xp2, cxm, vfx[c]);
+        if (wy && kcy_d > 0) dfy = masked_num(ym2, ym1, yp1, yp2, cym, vfy[c]);
         acc[1][c] -= dfx * a.i12x + dfy * a.i12y;
       }
     }
@@ -721,20 +837,6 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       T r[kNQ];
 #pragma unroll
       for (int c = 0; c < kNQ; ++c) r[c] = acc[0][c];
-      if (AT) {
-        // a plane next to a z face whose delay is k >= 1: the F_z values across it were left out
-        // of the scatter; add the AT sum (uniform across the plane but for the columns' PEs)
-        const int gzf = pmod(zf, nz);
-        const int tzf = gzf / a.ez, lzf = gzf - tzf * a.ez;
-        if (lzf < 2 || lzf >= a.ez - 2) {
-          const int k = a.delays[((tzf * a.py + ty) * a.px + tx) * 6 + (lzf < 2 ? 4 : 5)];
-          if (k > 0) {
-            const uint32_t oz = slab_off(a, 2, gx, gy, gzf);
-#pragma unroll
-            for (int c = 0; c < kNQ; ++c) r[c] -= at_sum<T>(a, 2, 4 + c, oz) * a.i12z;
-          }
-        }
-      }
       if (forced) {
         // f_c = 2 Re(sum_kz B_kz,c e^{i kz z}), B from LDS, e^{i kz z} for kz = 1, 2 from the table
         const int gzf = pmod(zf, nz);
@@ -785,11 +887,6 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       // the divergence of plane zc (next iteration) with this plane's delays; AT sums ahead
       kcx_d = kcx;
       kcy_d = kcy;
-#pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
-        bxd[mi] = bx[mi];
-        byd[mi] = by[mi];
-      }
       // consume what the last iteration fetched (the plane-only points of zc + 1, the column's
       // plane zc + 3), then fetch ahead: every lane fetches, at a valid address, the plane after
       // (zc + 2, zc + 4, wrapped), so that the wait counts on the fetches are exact
@@ -813,10 +910,14 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
           e_ = own_copy(e_);
         }
         zw.push(u_, v_, w_, t_, r_, e_);
-        s_pr[bn][0][py][px] = zw.get(0, 2);
-        s_pr[bn][1][py][px] = zw.get(1, 2);
-        s_pr[bn][2][py][px] = zw.get(2, 2);
-        s_pr[bn][3][py][px] = zw.get(3, 2);
+        if (kSub && gk > 0) {  // the window keeps the column's own values for later planes
+          put_ghost_prims(s_pr[bn], zc + 1);
+        } else {
+          s_pr[bn][0][py][px] = zw.get(0, 2);
+          s_pr[bn][1][py][px] = zw.get(1, 2);
+          s_pr[bn][2][py][px] = zw.get(2, 2);
+          s_pr[bn][3][py][px] = zw.get(3, 2);
+        }
       }
       {
         const uint32_t i = (uint32_t)pmod(zc + 4, nz) * plane + col + zero_after(t_);
@@ -857,30 +958,31 @@ __device__ __forceinline__ uint32_t xcd_major(uint32_t w, uint32_t nb) {
 }
 
 // MINW: waves per SIMD the register allocation must allow (occupancy target).
-template <typename T, int BX, int BY, int MINW, bool PUB, bool AT>
+template <typename T, int BX, int BY, int MINW, bool PUB, bool AT, bool SUB>
 __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, int mode) {
   const uint32_t gx = (uint32_t)a.gbx, gxy = gx * (uint32_t)a.gby;
   const uint32_t L = xcd_major(blockIdx.x, gridDim.x);
   const uint32_t bz = L / gxy, r = L - bz * gxy, by = r / gx, bx = r - by * gx;
-  stage_body<T, BX, BY, PUB, AT>(a, mode, (int)bx, (int)by, (int)bz, L);
+  stage_body<T, BX, BY, PUB, AT, SUB>(a, mode, (int)bx, (int)by, (int)bz, L);
 }
 
 // Batched stage: one launch over the workgroups of many runs.  work[b] = (run, local workgroup);
 // the run's arguments come from the device run table, so each run sees exactly the workgroup
 // decomposition (and therefore the arithmetic) of its own single-run launch.  A run executes in
 // the instantiation its own single-run step would use: the AT one where it reads delayed levels
-// at this stage (its `views` flag), the other one elsewhere; its workgroups leave the other
-// instantiation's launch at once.
-template <typename T, int BX, int BY, int MINW, bool PUB, bool AT>
+// at this stage (its `views` flag), the other one elsewhere, and of the two AT ones the one for its
+// tiles (at_ghost: aligned with its PEs); its workgroups leave the other instantiations' launches
+// at once.
+template <typename T, int BX, int BY, int MINW, bool PUB, bool AT, bool SUB>
 __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage_batch(const FArgs<T>* __restrict__ runs,
                                                                           const uint2* __restrict__ work,
                                                                           int mode) {
   const uint2 w = work[xcd_major(blockIdx.x, gridDim.x)];
   const FArgs<T> a = runs[w.x];
-  if ((a.views != 0) != AT) return;  // uniform across the workgroup
+  if ((a.views != 0) != AT || (AT && (a.at_ghost != 0) != SUB)) return;  // uniform across the workgroup
   const uint32_t per = (uint32_t)a.gbx * (uint32_t)a.gby;
   const uint32_t bz = w.y / per, r = w.y - bz * per, by = r / (uint32_t)a.gbx, bx = r - by * (uint32_t)a.gbx;
-  stage_body<T, BX, BY, PUB, AT>(a, mode, (int)bx, (int)by, (int)bz, w.y);
+  stage_body<T, BX, BY, PUB, AT, SUB>(a, mode, (int)bx, (int)by, (int)bz, w.y);
 }
 
 template <typename T>
@@ -922,6 +1024,7 @@ FArgs<T> pack(const StageArgs<T>& s, int zchunk) {
   a.gbx = (g.n[0] + 15) / 16;  // set to the launch tile's workgroup counts by the launchers
   a.gby = (g.n[1] + 3) / 4;
   a.views = 0;
+  a.at_ghost = s.at_ghost;
   a.publish = s.publish;
   a.store_dq = s.store_dq;
   a.i12x = s.cf.inv12h[0];
@@ -982,14 +1085,19 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
     const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid(gx * gy * gz), block(Tile<BX, BY>::NT);
     constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA);
-    if (s.publish && at)
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MP, true, true>), grid, block, dyn, stream, a, mode);
+    const bool sub = at && s.at_ghost;
+    if (s.publish && sub)
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, true, true>), grid, block, dyn, stream, a, mode);
+    else if (s.publish && at)
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MP, true, true, false>), grid, block, dyn, stream, a, mode);
     else if (s.publish)
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, false>), grid, block, dyn, stream, a, mode);
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, false, false>), grid, block, dyn, stream, a, mode);
+    else if (sub)
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, true, true>), grid, block, dyn, stream, a, mode);
     else if (at)
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MA, false, true>), grid, block, dyn, stream, a, mode);
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MA, false, true, false>), grid, block, dyn, stream, a, mode);
     else
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, false>), grid, block, dyn, stream, a, mode);
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, false, false>), grid, block, dyn, stream, a, mode);
     return hipGetLastError();
   }
 }
@@ -1006,7 +1114,10 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
 // and writes the sums of stage s into the s-th of three consecutive slot-sized regions of gv.
 // One thread serves the two readers of a face (layers 0, 1 or 2, 3), which share their delay and
 // the source points across it (each extrapolated once).  Readers whose face has k = 0 are not
-// written.
+// written.  For a run whose stages run on tiles aligned with its PEs (at_ghost), the x and y
+// entries hold the two extrapolated values instead (layers -2, -1 at the slots of readers 0, 1;
+// layers e, e+1 at those of readers 2, 3), which the stage kernel places in its halo; the sums are
+// formed from them as at_sum_of does.
 template <typename T>
 __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid,
                                              const T c0, const T c1, const T c2) {
@@ -1057,6 +1168,7 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
   const int tn = lower ? (t == 0 ? pd - 1 : t - 1) : (t == pd - 1 ? 0 : t + 1);
   // sources: lower face: layers 2, 3 of PE tn; upper face: layers 0, 1 of PE tn
   const int sl = lower ? 2 : 0;
+  const bool ghost = a.at_ghost != 0 && d < 2;
   T w[3][3];
 #pragma unroll
   for (int st = 0; st < 3; ++st) {
@@ -1086,9 +1198,10 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
       const T va = w[st][0] * a0 + w[st][1] * a1 + w[st][2] * a2;
       const T vb = w[st][0] * b0 + w[st][1] * b1 + w[st][2] * b2;
       // lower face: reader 0 = 1 va - 8 vb (offsets -2, -1), reader 1 = 1 vb (offset -2);
-      // upper face: reader 2 = -1 va (offset +2), reader 3 = 8 va - 1 vb (offsets +1, +2)
-      const T v0 = lower ? va - T(8) * vb : -va;
-      const T v1 = lower ? vb : T(8) * va - vb;
+      // upper face: reader 2 = -1 va (offset +2), reader 3 = 8 va - 1 vb (offsets +1, +2); or,
+      // for the x / y faces of a run on aligned tiles, the extrapolated values va, vb themselves
+      const T v0 = ghost ? va : at_sum_of<T>(lower, lower, va, vb);
+      const T v1 = ghost ? vb : at_sum_of<T>(lower, !lower, va, vb);
       T* g = gv + (uint32_t)st * a.rslot;
       g[dst + (uint32_t)c * ss] = v0;
       g[dst + jstride + (uint32_t)c * ss] = v1;
@@ -1153,6 +1266,7 @@ size_t fused_lds_bytes(int tile, size_t word, bool forced) {
 template <typename T>
 hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, bool at, hipStream_t stream) {
   if (fused_lds_bytes(tile, sizeof(T), a.force.table != nullptr) > kLdsBytes) return hipErrorInvalidConfiguration;
+  if (at && a.at_ghost && !tile_aligned(a.g, tile)) return hipErrorInvalidValue;  // halo values need aligned tiles
   constexpr bool f32 = sizeof(T) == 4;
   switch (tile) {
     case 0: return launch_cfg<T, 64, 8, f32 ? 4 : 2>(a, zchunk, mode, at, stream);
@@ -1187,7 +1301,7 @@ int64_t view_blocks(const Geom& g) { return (g.slab[0] + g.slab[1] + g.slab[2]) 
 
 namespace {
 template <typename T, int BX, int BY, int MINW>
-hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, bool forced, bool publish, bool at,
+hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, bool forced, bool publish, int at,
                             int mode, hipStream_t stream) {
   if constexpr (stage_static_lds<T, BX, BY>() > kLdsBytes) {
     return hipErrorInvalidConfiguration;
@@ -1196,14 +1310,26 @@ hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, b
     const dim3 grid((unsigned)nblk), block(Tile<BX, BY>::NT);
     const FArgs<T>* r = (const FArgs<T>*)runs;
     constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA);
-    if (publish && at)
-      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MP, true, true>), grid, block, dyn, stream, r, work, mode);
-    else if (publish)
-      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, false>), grid, block, dyn, stream, r, work, mode);
-    else if (at)
-      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MA, false, true>), grid, block, dyn, stream, r, work, mode);
-    else
-      hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, false>), grid, block, dyn, stream, r, work, mode);
+    if (at == 0) {
+      if (publish)
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, false, false>), grid, block, dyn, stream, r, work, mode);
+      else
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, false, false>), grid, block, dyn, stream, r, work, mode);
+    }
+    if (at & kAtMasked) {
+      if (publish)
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MP, true, true, false>), grid, block, dyn, stream, r, work, mode);
+      else
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MA, false, true, false>), grid, block, dyn, stream, r, work, mode);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (at & kAtGhost) {
+      if (publish)
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, true, true>), grid, block, dyn, stream, r, work, mode);
+      else
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, true, true>), grid, block, dyn, stream, r, work, mode);
+    }
     return hipGetLastError();
   }
 }
@@ -1211,7 +1337,7 @@ hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, b
 
 template <typename T>
 hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk, int tile, bool forced, bool publish,
-                              bool at, int mode, hipStream_t stream) {
+                              int at, int mode, hipStream_t stream) {
   if (nblk <= 0 || nblk > 0x7fffffff) return hipErrorInvalidValue;
   if (fused_lds_bytes(tile, sizeof(T), forced) > kLdsBytes) return hipErrorInvalidConfiguration;
   constexpr bool f32 = sizeof(T) == 4;
@@ -1240,8 +1366,8 @@ template size_t batch_arg_bytes<float>();
 template size_t batch_arg_bytes<double>();
 template void pack_batch_arg<float>(const StageArgs<float>&, int, int, int, void*);
 template void pack_batch_arg<double>(const StageArgs<double>&, int, int, int, void*);
-template hipError_t launch_fused_batch<float>(const void*, const uint2*, int64_t, int, bool, bool, bool, int, hipStream_t);
-template hipError_t launch_fused_batch<double>(const void*, const uint2*, int64_t, int, bool, bool, bool, int, hipStream_t);
+template hipError_t launch_fused_batch<float>(const void*, const uint2*, int64_t, int, bool, bool, int, int, hipStream_t);
+template hipError_t launch_fused_batch<double>(const void*, const uint2*, int64_t, int, bool, bool, int, int, hipStream_t);
 template hipError_t launch_at_sums_batch<float>(const void*, const uint2*, int64_t, const double*, hipStream_t);
 template hipError_t launch_at_sums_batch<double>(const void*, const uint2*, int64_t, const double*, hipStream_t);
 
