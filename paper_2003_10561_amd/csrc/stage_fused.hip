@@ -598,22 +598,37 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     const bool need_fx = (role == 0 || role == 2) && zin && mode != kModePublish;
     const bool need_fy = (role == 0 || role == 1) && zin && mode != kModePublish;
     const bool need_fz = valid && mode != kModePublish;
-    if (kSub && gk > 0) {
-      // a ghost of a delayed tile-PE face: its flux-plane entry is the extrapolated face-normal
-      // flux (it computes nothing)
-      if (zin && mode != kModePublish) {
-        const uint32_t o = gofs + (uint32_t)gz * gzs;
-        T F[kNQ];
+    if (kSub && gside >= 0) {
+      // a ghost column: while its tile-PE face is delayed, its flux-plane entry of this plane is
+      // the extrapolated face-normal flux and its LDS entry of the next plane (a buffer nobody
+      // reads in this iteration) the extrapolated primitives; both fetched in one round trip.
+      // The next plane's delay: this z-PE's, or the next z-PE's at its first plane (uniform).
+      const int zn = pmod(zc + 1, nz), tzn = zn / a.ez;
+      const int gkn = tzn == tz_c ? gk : (int)a.delays[((tzn * a.py + tty) * a.px + ttx) * 6 + gside];
+      if (gk > 0 || gkn > 0) {
+        const uint32_t o = gofs + (uint32_t)gz * gzs, on = gofs + (uint32_t)zn * gzs;
+        T F[kNQ], P[4];
 #pragma unroll
         for (int c = 0; c < kNQ; ++c) F[c] = a.gv[o + (uint32_t)(4 + c) * gss];
-        if (role == 2) {
 #pragma unroll
-          for (int c = 0; c < kNQ; ++c) s_fx[bc][c][py - 4][px - 2] = F[c];
-        } else {
+        for (int c = 0; c < 4; ++c) P[c] = a.gv[on + (uint32_t)c * gss];
+        if (gk > 0 && zin && mode != kModePublish) {
+          if (role == 2) {
 #pragma unroll
-          for (int c = 0; c < kNQ; ++c) s_fy[bc][c][py - 2][px - 4] = F[c];
+            for (int c = 0; c < kNQ; ++c) s_fx[bc][c][py - 4][px - 2] = F[c];
+          } else {
+#pragma unroll
+            for (int c = 0; c < kNQ; ++c) s_fy[bc][c][py - 2][px - 4] = F[c];
+          }
+        }
+        if (gkn > 0 && zc <= z1) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) s_pr[bd][c][py][px] = P[c];
         }
       }
+    }
+    if (kSub && gk > 0) {
+      // computes nothing
     } else if (need_fx || need_fy || need_fz || pub) {
       T G[kNGrad];
       // derivatives of u, v, w, T: x and y from the LDS plane, z from the window.  Where a stencil
@@ -910,9 +925,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
           e_ = own_copy(e_);
         }
         zw.push(u_, v_, w_, t_, r_, e_);
-        if (kSub && gk > 0) {  // the window keeps the column's own values for later planes
-          put_ghost_prims(s_pr[bn], zc + 1);
-        } else {
+        if (!(kSub && gk > 0)) {  // (a ghost's entry is in place; its window keeps its own values)
           s_pr[bn][0][py][px] = zw.get(0, 2);
           s_pr[bn][1][py][px] = zw.get(1, 2);
           s_pr[bn][2][py][px] = zw.get(2, 2);
@@ -1060,6 +1073,13 @@ constexpr int pub_at_waves(int ma) {
   return sizeof(T) == 4 && Tile<BX, BY>::NT <= 256 ? 3 : ma;
 }
 
+// Occupancy target of the instantiations for aligned tiles (SUB): in FP32 they fit the registers of
+// 4 waves per SIMD (the publishing one with 2 or 3 spilled), whatever the tile's own target.
+template <typename T>
+constexpr int sub_waves(int minw) {
+  return sizeof(T) == 4 ? 4 : minw;
+}
+
 // Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950).
 template <typename T, int BX, int BY>
 constexpr size_t stage_static_lds() {
@@ -1084,16 +1104,16 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
     a.gby = (int)gy;
     const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid(gx * gy * gz), block(Tile<BX, BY>::NT);
-    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA);
+    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T>(MINW);
     const bool sub = at && s.at_ghost;
     if (s.publish && sub)
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, true, true>), grid, block, dyn, stream, a, mode);
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MS, true, true, true>), grid, block, dyn, stream, a, mode);
     else if (s.publish && at)
       hipLaunchKernelGGL((k_stage<T, BX, BY, MP, true, true, false>), grid, block, dyn, stream, a, mode);
     else if (s.publish)
       hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, false, false>), grid, block, dyn, stream, a, mode);
     else if (sub)
-      hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, false, true, true>), grid, block, dyn, stream, a, mode);
+      hipLaunchKernelGGL((k_stage<T, BX, BY, MS, false, true, true>), grid, block, dyn, stream, a, mode);
     else if (at)
       hipLaunchKernelGGL((k_stage<T, BX, BY, MA, false, true, false>), grid, block, dyn, stream, a, mode);
     else
@@ -1309,7 +1329,7 @@ hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, b
     const size_t dyn = forced ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid((unsigned)nblk), block(Tile<BX, BY>::NT);
     const FArgs<T>* r = (const FArgs<T>*)runs;
-    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA);
+    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T>(MINW);
     if (at == 0) {
       if (publish)
         hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, false, false>), grid, block, dyn, stream, r, work, mode);
@@ -1326,9 +1346,9 @@ hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, b
     }
     if (at & kAtGhost) {
       if (publish)
-        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, true, true>), grid, block, dyn, stream, r, work, mode);
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MS, true, true, true>), grid, block, dyn, stream, r, work, mode);
       else
-        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, false, true, true>), grid, block, dyn, stream, r, work, mode);
+        hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MS, false, true, true>), grid, block, dyn, stream, r, work, mode);
     }
     return hipGetLastError();
   }
