@@ -127,6 +127,69 @@ def test_rhs_random_delays_history_levels(n, p):
     compare_fields(g.rhs().cpu().numpy(), o.rhs(), 1e-12, "rhs at next step")
 
 
+def _face_pairs(tab_step, p, d):
+    """(delay of PE t's upper face along d, delay of its upper neighbour's lower face) for every PE."""
+    px, py, pz = p
+    out = []
+    for tz in range(pz):
+        for ty in range(py):
+            for tx in range(px):
+                t = [tx, ty, tz]
+                nb = list(t)
+                nb[d] = (nb[d] + 1) % p[d]
+                i = (tz * py + ty) * px + tx
+                j = (nb[2] * py + nb[1]) * px + nb[0]
+                out.append((int(tab_step[i, 2 * d + 1]), int(tab_step[j, 2 * d])))
+    return out
+
+
+def test_halo_substitution_cases():
+    """Delayed stages on tiles aligned with the PEs put extrapolated values into the tile halo; the
+    halo columns that still compute mask their own delayed faces.  PEs of 16 x 24 x 16 with 16x8
+    tiles: every tile touches both x faces of its PE, and along y there are face tiles and an interior
+    one.  A seeded explicit table holds, across x and y faces, every combination of the two sides'
+    delays (reader side delayed / neighbour delayed / both / neither; checked below), and delayed z
+    faces.  FP64 fields, statistics and the RHS match the oracle; the 32x4 tile (not aligned: masked
+    operands everywhere) gives bitwise the same fields in FP64 and in FP32."""
+    n, p = (48, 48, 32), (3, 2, 2)
+    say("case halo substitution 48x48x32 on 3x2x2 PEs, explicit delays, 16x8 vs 32x4")
+    nlev, nsteps = 6, 4
+    q = history_levels(n, nlev, 4321)
+    nt = p[0] * p[1] * p[2]
+    rng = np.random.default_rng(4321)
+    tab = np.zeros((nlev - 1 + nsteps + 1, nt, 6), dtype=np.int8)
+    tab[nlev - 1:nlev - 1 + nsteps] = rng.integers(0, 4, size=(nsteps, nt, 6))
+    for d in (0, 1):
+        seen = set()
+        for s in range(nlev - 1, nlev - 1 + nsteps):
+            seen |= {(a > 0, b > 0) for a, b in _face_pairs(tab[s], p, d)}
+        assert seen == {(False, False), (False, True), (True, False), (True, True)}, (d, seen)
+    assert (tab[nlev - 1:, :, 4:] > 0).any()
+
+    def run(prec, tile):
+        s = atns.Sim(atns.Config(n=n, p=p, dt=0.01, mu_ref=0.02, max_delay=3, precision=prec))
+        s.set_tuning(tile, 8)  # z chunks of 8: chunk ends inside and at the z-PE faces
+        s.init_field(q, nlev)
+        s.set_delay_schedule(atns.EXPLICIT, table=tab)
+        return s
+
+    g = run("fp64", 5)
+    o = Oracle(OracleConfig(n=n, p=p, dt=0.01, mu_ref=0.02, max_delay=3))
+    o.init_field(q, nlev)
+    o.set_schedule(atns.EXPLICIT, table=tab)
+    compare_fields(g.rhs().cpu().numpy(), o.rhs(), 1e-12, "rhs (aligned tiles)")
+    h64, a32, b32 = run("fp64", 3), run("fp32", 5), run("fp32", 3)
+    for _ in range(nsteps):
+        for s in (g, h64, a32, b32):
+            s.rk_step(1)
+        o.rk_step(1)
+        compare_stats(g.stats(), o.stats(), TOL64)
+    f = g.get_field()
+    compare_fields(f, o.field(), TOL64, f"after {nsteps} steps (aligned tiles)")
+    assert np.array_equal(f, h64.get_field())
+    assert np.array_equal(a32.get_field(), b32.get_field())
+
+
 def test_tile_shapes_agree_on_wide_pes():
     """PEs of 48 x 24 x 16: the 16x8 tile has workgroups whose columns and halos all lie inside one
     PE along x and y (no x/y stencil of theirs crosses a face) next to workgroups at the faces; a
