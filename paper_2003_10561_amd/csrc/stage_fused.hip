@@ -536,6 +536,29 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     for (int c = 0; c < 4; ++c) dst[c][py][px] = a.gv[o + (uint32_t)c * gss];
   };
   if (kSub) plane_delays(z0 - 2);
+  // SUB: a halo column next to an x face forms the AT sums of its x derivatives (used while its own
+  // PE's face is delayed and the tile's is not) a plane ahead: the operands of plane zc + 1 are
+  // fetched at the top of iteration zc into the registers the tile's columns use for the finalize
+  // fetch (free in halo columns), and the sums go to this thread's LDS slot when that fetch is
+  // retired, for the next iteration's gradients; so the halo waves do not wait in their gradients.
+  // (The publishing instantiation fetches them when it needs them: measured faster there.)
+  constexpr bool kHv = kSub && !PUB;
+  __shared__ T s_hv[kHv ? 4 : 1][kHv ? TL::NY2 + TL::NX2 : 1];
+  const bool hx = kHv && (role == 1 || role == 2) && near_x;
+  const int hslot = kSub ? max(tid - TL::NOWN, 0) : 0;
+  auto hx_fetch = [&](int zpl) {
+    const uint32_t o = (uint32_t)pmod(zpl, nz) * zsx + opx - (uint32_t)(lxe < 2 ? lxe : lxe - a.ex + 2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      fq[c] = a.gv[o + (uint32_t)c * a.slab0];
+      fd[c] = a.gv[o + 1 + (uint32_t)c * a.slab0];
+    }
+  };
+  auto hx_store = [&]() {
+    const bool lo = lxe < 2, outer = lxe == 0 || lxe == a.ex - 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s_hv[c][hslot] = at_sum_of<T>(lo, outer, fq[c], fd[c]);
+  };
 
   // window plane z0, then the LDS plane z0 - 2 (buffer parity (z + 2) & 1)
   if (column) {
@@ -573,6 +596,10 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   __syncthreads();
 
   if (!kSub) plane_delays(z0 - 2);
+  if (hx) {
+    hx_fetch(z0 - 2);
+    hx_store();
+  }
 
   // Iteration zc: fluxes of plane zc (LDS buffers of parity zc), x-y divergence of plane zc - 1,
   // update of plane zc - 2, then the window and LDS plane for zc + 1; one barrier per plane.
@@ -627,6 +654,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         }
       }
     }
+    if (hx && zc <= z1) hx_fetch(zc + 1);  // after the ghost fetches, which are waited for at once
     if (kSub && gk > 0) {
       // computes nothing
     } else if (need_fx || need_fy || need_fz || pub) {
@@ -645,13 +673,18 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
         sy[c] = kMask ? vy[c] : T(0);
       }
       if (kSub && wx && kcx > 0) {
-        // a halo column next to its own delayed x face: its AT sums from the two extrapolated
-        // values at its face's reader slots
-        const uint32_t o = (uint32_t)gz * zsx + opx - (uint32_t)(lxe < 2 ? lxe : lxe - a.ex + 2);
-        const bool lo = lxe < 2, outer = lxe == 0 || lxe == a.ex - 1;
+        // a halo column next to its own delayed x face: its AT sums, formed a plane ahead, or from
+        // the two extrapolated values at its face's reader slots
+        if (kHv) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sx[c] = at_sum_of<T>(lo, outer, a.gv[o + (uint32_t)c * a.slab0],
-                                                          a.gv[o + 1 + (uint32_t)c * a.slab0]);
+          for (int c = 0; c < 4; ++c) sx[c] = s_hv[c][hslot];
+        } else {
+          const uint32_t o = (uint32_t)gz * zsx + opx - (uint32_t)(lxe < 2 ? lxe : lxe - a.ex + 2);
+          const bool lo = lxe < 2, outer = lxe == 0 || lxe == a.ex - 1;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) sx[c] = at_sum_of<T>(lo, outer, a.gv[o + (uint32_t)c * a.slab0],
+                                                            a.gv[o + 1 + (uint32_t)c * a.slab0]);
+        }
       }
       if (kSub && wy && kcy > 0) {
         const uint32_t o = (uint32_t)gz * zsy + opy - (uint32_t)(lye < 2 ? lye : lye - a.ey + 2) * (uint32_t)nx;
@@ -889,6 +922,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     // for them happens now, not at the next write of their registers, after later fetches)
 #pragma unroll
     for (int c = 0; c < 5; ++c) asm volatile("" ::"v"(fq[c]), "v"(fd[c]));
+    if (hx && zc <= z1) hx_store();  // the sums of plane zc + 1
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -1080,12 +1114,13 @@ constexpr int sub_waves(int minw) {
   return sizeof(T) == 4 ? 4 : minw;
 }
 
-// Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950).
+// Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950); the halo AT-sum
+// slots of the aligned-tile instantiations are counted for all.
 template <typename T, int BX, int BY>
 constexpr size_t stage_static_lds() {
   using TL = Tile<BX, BY>;
   return sizeof(T) * (2 * (4 * TL::LH * TL::LW + 5 * BY * (BX + 4) + 5 * (BY + 4) * BX) +
-                      (sizeof(T) == 4 ? 1 : 26 * TL::NCOL)) +
+                      (sizeof(T) == 4 ? 1 : 26 * TL::NCOL) + 4 * (TL::NY2 + TL::NX2)) +
          8 * kNQ * TL::NOWN;
 }
 
