@@ -235,7 +235,7 @@ ATNS_API int at_batch_get_stage_tuning(at_batch* batch, int32_t* tile_sync, int3
 
 /* Choose the launch shapes: looks up the device, the members' shapes and the fraction f of their
  * remaining scheduled steps that read delayed levels in cache_path (JSON lines; NULL = no cache);
- * otherwise times, for every feasible (tile, z chunk) (z chunks 8, 16, ..., 256, up to the members'
+ * otherwise times, for every feasible (tile, z chunk) (z chunks 8, 16, ..., 512, up to the members'
  * largest n_z), `reps` synchronous trial stages and (if
  * f > 0) `reps` delayed ones (each member at the delays of its first delayed step), keeps the
  * fastest shape of each kind (as at_batch_set_stage_tuning) and appends them to the cache.  A trial rewrites only buffers

@@ -514,7 +514,7 @@ int do_autotune(at_batch* b, const char* cache, int reps, double* best_ms) {
   for (const at_sim* s : b->runs) maxz = std::max(maxz, s->cfg.n[2]);
   double best_s = 1e300, best_d = 1e300;
   int bt = b->tile, bz = b->zchunk, btd = b->tile_d, bzd = b->zchunk_d;
-  static const int kZ[] = {8, 16, 32, 64, 128, 256};
+  static const int kZ[] = {8, 16, 32, 64, 128, 256, 512};
   for (int tile = 0; tile < kTileCount; ++tile) {
     if (!tile_fits(b, tile)) continue;
     for (int zc : kZ) {
