@@ -104,7 +104,9 @@ ATNS_API const char* at_last_error(void);
  * state buffers (a stage reads one and writes the other), the RK register, the ring of
  * published face layers: (max_delay + 3) levels x 9 components (u, v, w, T and the face-normal flux of the five
  * conserved variables) x 4 (1/ex + 1/ey + 1/ez) N^3 points, and three level-sized buffers of the
- * AT sums of the face-layer readers (one per RK stage of a step), plus small reduction scratch. */
+ * AT sums of the face-layer readers (one per RK stage of a step; for the x and y faces, when the
+ * delayed-stage tile is aligned with the PEs, the extrapolated values themselves), plus small
+ * reduction scratch. */
 ATNS_API size_t at_workspace_bytes(const at_config* cfg);
 
 /* Create a simulation handle.  dev_workspace: device memory of at least at_workspace_bytes(cfg)
@@ -173,8 +175,11 @@ ATNS_API int at_get_tuning(at_sim* sim, int32_t* tile, int32_t* zchunk);
 
 /* Separate launch shapes for the stages that read no delayed level (tile_sync, zchunk_sync) and
  * for those that do (tile_delayed, zchunk_delayed): the two are compiled differently (the AT code
- * of Sec. 2.1 is left out of the first), and their fastest shapes differ.  Same meaning and errors
- * as at_set_tuning. */
+ * of Sec. 2.1 is left out of the first), and their fastest shapes can differ.  A delayed-stage tile
+ * whose width and height divide the PE edges (aligned) puts the extrapolated values of Sec. 2.1
+ * into the tile halo; other tiles replace the crossing half of each stencil by the reader's AT sum.
+ * The two round identically, so fields are the same bit for bit.  Same meaning and errors as
+ * at_set_tuning. */
 ATNS_API int at_set_stage_tuning(at_sim* sim, int32_t tile_sync, int32_t zchunk_sync, int32_t tile_delayed,
                                  int32_t zchunk_delayed);
 ATNS_API int at_get_stage_tuning(at_sim* sim, int32_t* tile_sync, int32_t* zchunk_sync, int32_t* tile_delayed,
