@@ -190,6 +190,49 @@ def test_halo_substitution_cases():
     assert np.array_equal(a32.get_field(), b32.get_field())
 
 
+def test_halo_substitution_every_tile_shape():
+    """PEs of 64 x 8 x 16: every tile shape but 16x16 is aligned with them (halo substitution, each
+    shape its own instantiation), 16x16 is not (masked operands).  Seeded explicit delays 0..3 over
+    3 steps.  FP32: all shapes give bitwise the same fields, and the 64x8 one (the benchmark's)
+    matches the FP64 oracle within the FP32 bound of test_fp32_error_against_fp64_oracle.  FP64:
+    16x8 matches the oracle, 32x4 gives bitwise the same fields."""
+    n, p = (128, 16, 32), (2, 2, 2)
+    say("case halo substitution, every tile shape, 128x16x32 on 2x2x2 PEs")
+    nlev, nsteps = 6, 3
+    q = history_levels(n, nlev, 6408)
+    rng = np.random.default_rng(6408)
+    tab = np.zeros((nlev - 1 + nsteps + 1, 8, 6), dtype=np.int8)
+    tab[nlev - 1:nlev - 1 + nsteps] = rng.integers(0, 4, size=(nsteps, 8, 6))
+
+    def run(prec, tile):
+        s = atns.Sim(atns.Config(n=n, p=p, dt=0.01, mu_ref=0.02, max_delay=3, precision=prec))
+        try:
+            s.set_tuning(tile, 8)
+        except atns.AtError:
+            s.close()
+            return None  # does not fit the LDS at this precision
+        s.init_field(q, nlev)
+        s.set_delay_schedule(atns.EXPLICIT, table=tab)
+        s.rk_step(nsteps)
+        f = s.get_field()
+        s.close()
+        return f
+
+    o = Oracle(OracleConfig(n=n, p=p, dt=0.01, mu_ref=0.02, max_delay=3))
+    o.init_field(q, nlev)
+    o.set_schedule(atns.EXPLICIT, table=tab)
+    o.rk_step(nsteps)
+    ref = o.field()
+    f32 = {t: run("fp32", t) for t in range(atns.N_TILES)}
+    assert all(f is not None for f in f32.values())
+    compare_fields(f32[0], ref, 2e-6, "fp32 64x8 (aligned)")
+    for t in range(1, atns.N_TILES):
+        assert np.array_equal(f32[t], f32[0]), t
+    f64 = run("fp64", 5)
+    compare_fields(f64, ref, TOL64, "fp64 16x8 (aligned)")
+    assert np.array_equal(run("fp64", 3), f64)
+
+
 def test_tile_shapes_agree_on_wide_pes():
     """PEs of 48 x 24 x 16: the 16x8 tile has workgroups whose columns and halos all lie inside one
     PE along x and y (no x/y stencil of theirs crosses a face) next to workgroups at the faces; a
