@@ -51,6 +51,7 @@ struct ora_sim {
   int32_t kf[NFORCE][3];
   int64_t step;
   double tot_rk[NQ];
+  int ab2_prev;          /* dq holds dt f^{n-1} from an Adams-Bashforth step */
   int initialised;
   int err;
 };
@@ -526,6 +527,7 @@ int ora_init_field(ora_sim* s, const double* q, int32_t nlev) {
   }
   memcpy(s->q, q + (int64_t)(nlev - 1) * NQ * N, sizeof(double) * NQ * N);
   memset(s->dq, 0, sizeof(double) * NQ * N);
+  s->ab2_prev = 0;
   s->step = nlev - 1;
   const double vol = s->h[0] * s->h[1] * s->h[2];
   for (int c = 0; c < NQ; c++) {
@@ -567,6 +569,41 @@ int ora_rk_step(ora_sim* s, int32_t nsteps) {
         s->tot_rk[c] += B * acc * vol;
       }
     }
+    s->step++;
+  }
+  s->ab2_prev = 0;
+  return ORA_OK;
+}
+
+/* Second-order Adams-Bashforth (Sec. 2.2, Eq. time_ab with T = 2, beta_0 = 3/2, beta_1 = -1/2):
+ * Q^{n+1} = Q^n + dt (3/2 f^n - 1/2 f^{n-1}).  f^n is evaluated once per step at t_n (AT
+ * extrapolation at kappa = k, i.e. c_s = 0), publishing level n; f^{n-1} is kept from the previous
+ * step (dq holds dt f^{n-1}).  A step with no stored f^{n-1} (the first after initialisation or
+ * after Runge-Kutta steps) is forward Euler. */
+int ora_ab2_step(ora_sim* s, int32_t nsteps) {
+  if (!s || nsteps < 0) return ORA_E_INVAL;
+  if (!s->initialised) return ORA_E_STATE;
+  const int64_t N = s->npts;
+  const double dt = s->c.dt;
+  const double vol = s->h[0] * s->h[1] * s->h[2];
+  for (int it = 0; it < nsteps; it++) {
+    int rc = eval_rhs(s, s->q, 0, 1, s->rhs);
+    if (rc) return rc;
+    const int prev = s->ab2_prev;
+    for (int c = 0; c < NQ; c++) {
+      double acc = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : acc)
+      for (int64_t i = 0; i < N; i++) {
+        const int64_t j = c * N + i;
+        const double d = dt * s->rhs[j];
+        const double inc = prev ? 1.5 * d - 0.5 * s->dq[j] : d;
+        s->dq[j] = d;
+        s->q[j] = s->q[j] + inc;
+        acc += inc;
+      }
+      s->tot_rk[c] += acc * vol;
+    }
+    s->ab2_prev = 1;
     s->step++;
   }
   return ORA_OK;

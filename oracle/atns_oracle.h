@@ -58,6 +58,9 @@ int ora_get_schedule(const ora_sim* s, int8_t* out, int64_t n_steps);
 int ora_set_forcing(ora_sim* s, const double* fhat, int64_t n_steps);
 int ora_rhs(ora_sim* s, double* out);            /* [5][N] at the current state, c = 0 */
 int ora_rk_step(ora_sim* s, int32_t nsteps);
+/* nsteps second-order Adams-Bashforth steps (Sec. 2.2, Eq. time_ab); the first with no stored
+ * f^{n-1} (after initialisation or Runge-Kutta steps) is forward Euler. */
+int ora_ab2_step(ora_sim* s, int32_t nsteps);
 int ora_stats(ora_sim* s, double* out);          /* ORA_ST_COUNT doubles */
 int ora_get_field(const ora_sim* s, double* q);  /* [5][N] */
 int64_t ora_step(const ora_sim* s);

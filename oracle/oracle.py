@@ -94,6 +94,7 @@ def _load():
         lib.ora_set_forcing.argtypes = [vp, dp, i64]
         lib.ora_rhs.argtypes = [vp, dp]
         lib.ora_rk_step.argtypes = [vp, i32]
+        lib.ora_ab2_step.argtypes = [vp, i32]
         lib.ora_stats.argtypes = [vp, dp]
         lib.ora_get_field.argtypes = [vp, dp]
         lib.ora_get_flux.argtypes = [vp, dp]
@@ -182,6 +183,11 @@ class Oracle:
 
     def rk_step(self, nsteps=1):
         self._chk("rk_step", self.lib.ora_rk_step(self.h, int(nsteps)))
+
+    def ab2_step(self, nsteps=1):
+        """Second-order Adams-Bashforth steps (Sec. 2.2, Eq. time_ab); forward Euler where no
+        f^{n-1} is stored (after initialisation or Runge-Kutta steps)."""
+        self._chk("ab2_step", self.lib.ora_ab2_step(self.h, int(nsteps)))
 
     def stats(self) -> dict:
         out = np.zeros(len(STAT_NAMES))

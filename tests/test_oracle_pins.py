@@ -347,6 +347,59 @@ def test_rk3_entropy_wave_one_step(p):
     np.testing.assert_allclose(out[4], 1.0 / 0.4 + 1.5 * U * U * rho1, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("p", [(1, 1, 1), (2, 2, 2)])
+def test_ab2_entropy_wave_closed_form(p):
+    """Second-order Adams-Bashforth (Sec. 2.2, Eq. time_ab, beta = (3/2, -1/2)) on the inviscid
+    entropy wave of test_rk3_entropy_wave_one_step: each Fourier mode is y' = lambda y, so after a
+    forward-Euler start y_n = A r1^n + B r2^n, with r1, r2 the roots of the method's characteristic
+    polynomial r^2 - (1 + 3z/2) r + z/2 = 0 (z = lambda dt), A + B = 1 and A r1 + B r2 = 1 + z."""
+    N, U, amp = 16, 0.3, 0.2
+    X, Y, Z = F.grid((N, N, N))
+    th = X + Y + Z
+    rho = 1.0 + amp * np.sin(th)
+    q = F.conservative(rho, *([U + 0 * rho] * 3), 1.0 / rho)
+    dt, nsteps = 0.05, 5
+    o = Oracle(cfg_for((N, N, N), p, dt=dt, mu=0.0))
+    o.init_field(q)
+    o.set_schedule(SYNC, n_steps=nsteps + 1)
+    o.ab2_step(nsteps)
+    z = -3j * U * F.modified_wavenumber(1, 2 * math.pi / N) * dt
+    b = 1 + 1.5 * z
+    disc = np.sqrt(b * b - 2 * z + 0j)
+    r1, r2 = (b + disc) / 2, (b - disc) / 2
+    B = (1 + z - r1) / (r2 - r1)
+    A = 1 - B
+    g = A * r1 ** nsteps + B * r2 ** nsteps
+    rho_n = 1.0 + amp * np.imag(g * np.exp(1j * th))
+    out = o.field()
+    np.testing.assert_allclose(out[0], rho_n, rtol=0, atol=1e-13)
+    for c in range(1, 4):
+        np.testing.assert_allclose(out[c], U * rho_n, rtol=0, atol=1e-13)
+    assert o.step == nsteps
+
+
+def test_ab2_second_order_in_time():
+    """Sec. 2.2: the AB scheme of order 2.  On a smooth viscous field (synchronous derivatives),
+    the state at a fixed time from dt, dt/2, dt/4 differs from a Runge-Kutta reference at dt/32 by
+    errors whose ratios are ~4 (forward Euler would give ~2)."""
+    n = 16
+    q = W.make_field(n, 11, 0.3)
+    dt0 = W.default_dt(q)
+    mu = W.default_mu(n)
+
+    def run(dt, steps, ab2):
+        o = Oracle(cfg_for((n, n, n), (2, 2, 2), dt=dt, mu=mu))
+        o.init_field(q)
+        o.set_schedule(SYNC, n_steps=steps + 1)
+        (o.ab2_step if ab2 else o.rk_step)(steps)
+        return o.field()
+
+    ref = run(dt0 / 32, 256, False)
+    errs = [np.linalg.norm(run(dt0 / m, 8 * m, True) - ref) for m in (1, 2, 4)]
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(3.4 < r < 4.6 for r in ratios), (errs, ratios)
+
+
 def test_uniform_state_any_schedule():
     """Constant state: every flux is uniform and the extrapolation weights sum to one, so the RHS
     vanishes whatever the delays."""
