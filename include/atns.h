@@ -151,6 +151,14 @@ ATNS_API int at_rhs(at_sim* sim, void* dev_out);
  * Asynchronous: returns after enqueueing.  Errors: AT_E_STATE, AT_E_SCHEDULE, AT_E_HIP. */
 ATNS_API int at_rk_step(at_sim* sim, int32_t n_steps);
 
+/* Enqueue n_steps steps of second-order Adams-Bashforth (Sec. 2.2, Eq. time_ab with T = 2):
+ * Q^{n+1} = Q^n + dt (3/2 f^n - 1/2 f^{n-1}), one RHS per step at t_n, which publishes level n;
+ * a delayed face extrapolates levels n-k, n-k-1, n-k-2 to t_n (kappa = k, the Appendix B
+ * weights).  dt f^n is kept in the RK register for the next step, so a step with no stored
+ * f^{n-1} (the first after at_init_field, at_rk_step or a batch step) is forward Euler.  Not
+ * available through batches.  Asynchronous.  Errors: AT_E_STATE, AT_E_SCHEDULE, AT_E_HIP. */
+ATNS_API int at_ab2_step(at_sim* sim, int32_t n_steps);
+
 /* Statistics of the current state (synchronous derivatives on the whole periodic grid; global
  * reductions are the only all-PE operations, as in Sec. 3.1) into *out.  Synchronises the stream.
  * Errors: AT_E_STATE, AT_E_HIP. */

@@ -20,7 +20,7 @@ FP64, FP32 = 0, 1
 SYNC, CAA, SAA, EXPLICIT = 0, 1, 2, 3
 N_FORCE = 40
 EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "at_init_field",
-            "at_set_delay_schedule", "at_set_forcing", "at_rhs", "at_rk_step", "at_stats",
+            "at_set_delay_schedule", "at_set_forcing", "at_rhs", "at_rk_step", "at_ab2_step", "at_stats",
             "at_get_field", "at_field_device", "at_destroy", "at_set_kernel_timing",
             "at_kernel_timing", "at_kernel_name", "at_set_tuning", "at_get_tuning",
             "at_set_stage_tuning", "at_get_stage_tuning",
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     lib.at_set_forcing.argtypes = [vp, dp, i64]
     lib.at_rhs.argtypes = [vp, vp]
     lib.at_rk_step.argtypes = [vp, i32]
+    lib.at_ab2_step.argtypes = [vp, i32]
     lib.at_stats.argtypes = [vp, C.POINTER(_Stats)]
     lib.at_get_field.argtypes = [vp, dp]
     lib.at_field_device.argtypes = [vp, C.POINTER(vp)]
@@ -247,6 +248,10 @@ class Sim:
 
     def rk_step(self, n_steps: int = 1):
         _check("at_rk_step", self.lib.at_rk_step(self.h, int(n_steps)))
+
+    def ab2_step(self, n_steps: int = 1):
+        """Second-order Adams-Bashforth steps (at_ab2_step)."""
+        _check("at_ab2_step", self.lib.at_ab2_step(self.h, int(n_steps)))
 
     def stats(self) -> dict:
         s = _Stats()

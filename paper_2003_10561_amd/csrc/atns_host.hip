@@ -290,6 +290,7 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
   const double vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
   for (int c = 0; c < kNQ; ++c) s->tot_init[c] = st[c] * vol;
   s->step = nlev - 1;
+  s->ab2_prev = 0;
   s->initialised = 1;
   return AT_OK;
 }
@@ -325,6 +326,42 @@ int do_steps(at_sim* s, int nsteps) {
       HIP_TRY(launch_hooked<T>(s, a, kModeStepH, s->step_delayed[(size_t)s->step] != 0));
       s->qcur = 1 - s->qcur;
     }
+    s->step++;
+  }
+  return AT_OK;
+}
+
+// Second-order Adams-Bashforth steps (Sec. 2.2, Eq. time_ab, beta = 3/2, -1/2): one stage per
+// step at t_n (the AT sums of c_s = 0, the first of the three regions), publishing level n; the
+// register keeps dt f^n for the next step.  Without a stored dt f^{n-1} the step is forward Euler
+// (the Runge-Kutta update with A = 0, B = 1).
+template <typename T>
+int do_ab2_steps(at_sim* s, int nsteps) {
+  const size_t row = (size_t)s->g.ntiles * 6;
+  if (nsteps > 0)
+    s->tot_used = std::max({s->tot_used, fused_blocks(s->g, s->tile, s->zchunk), fused_blocks(s->g, s->tile_d, s->zchunk_d)});
+  for (int it = 0; it < nsteps; ++it) {
+    StageArgs<T> a = base_args<T>(s);
+    a.delays = s->d_sched + (size_t)s->step * row;
+    a.step = s->step;
+    a.step_mod_r = (int)(s->step % s->g.R);
+    if (s->cfg.forcing) {
+      T* tab = (T*)(s->ws + s->L.force_table);
+      HIP_TRY(launch_force_table<T>(s->g, s->d_fhat + (size_t)s->step * kNForce * 6, s->d_wv,
+                                    s->d_wv + kNForce, s->npair, tab,
+                                    (const T*)(s->ws + s->L.phase_x), s->stream, s->timer));
+      a.force.table = tab;
+    }
+    a.gv = a.gv_out;
+    a.rk_a = T(0);
+    a.rk_b = s->ab2_prev ? T(1.5) : T(1);
+    a.c_prev = s->ab2_prev ? T(-0.5) : T(0);
+    a.publish = 1;
+    a.store_dq = 1;
+    if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
+    HIP_TRY(launch_hooked<T>(s, a, kModeStepH, s->step_delayed[(size_t)s->step] != 0));
+    s->qcur = 1 - s->qcur;
+    s->ab2_prev = 1;
     s->step++;
   }
   return AT_OK;
@@ -517,7 +554,17 @@ int at_rk_step(at_sim* s, int32_t n_steps) {
   if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
   int rc = check_step_tables(s, s->step, n_steps);
   if (rc) return rc;
+  s->ab2_prev = 0;  // the register now holds the Runge-Kutta one
   return s->cfg.precision == AT_FP32 ? do_steps<float>(s, n_steps) : do_steps<double>(s, n_steps);
+}
+
+int at_ab2_step(at_sim* s, int32_t n_steps) {
+  if (!s) return fail(AT_E_INVAL, "NULL handle");
+  if (n_steps < 0) return fail(AT_E_INVAL, "n_steps < 0");
+  if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
+  int rc = check_step_tables(s, s->step, n_steps);
+  if (rc) return rc;
+  return s->cfg.precision == AT_FP32 ? do_ab2_steps<float>(s, n_steps) : do_ab2_steps<double>(s, n_steps);
 }
 
 int at_stats(at_sim* s, at_stats_t* out) {

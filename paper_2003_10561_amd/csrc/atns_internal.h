@@ -72,6 +72,7 @@ struct StageArgs {
   int64_t step;       // absolute step index n
   int step_mod_r;     // n mod R: ring slot of level n
   T rk_a, rk_b, dt;
+  T c_prev;           // Adams-Bashforth: Q += rk_b dQ + c_prev dQ_prev (dQ = dt RHS); 0 for RK
   int publish;        // stage 1: write level n into the ring
   int store_dq;       // 0 in the last stage (the register is not read again)
   int at_ghost;       // the delayed stages of this step run on tiles aligned with the PEs: the x / y

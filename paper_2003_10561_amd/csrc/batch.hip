@@ -310,6 +310,7 @@ int do_batch_steps(at_batch* b, int K) {
     s->tot_used = std::max({s->tot_used, fused_blocks(s->g, b->tile, run_zchunk(b, s, 0)),
                             fused_blocks(s->g, b->tile_d, run_zchunk(b, s, 1))});
     s->step += K;
+    s->ab2_prev = 0;  // Runge-Kutta steps: the register no longer holds dt f^{n-1}
     s->qcur ^= (K & 1);
   }
   return AT_OK;

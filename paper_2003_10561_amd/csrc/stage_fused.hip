@@ -59,6 +59,7 @@ struct FArgs {
   T i12x, i12y, i12z, gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
   T rk_a, rk_b, dt;
   double vol;
+  T c_prev;  // coefficient of the stored register in the update (Adams-Bashforth; 0 for RK)
 };
 
 template <typename T>
@@ -317,7 +318,8 @@ struct ZWin<T, NCOL, false> {
 // tile's columns evaluate the central form; halo columns that compute (their own PE's face delayed,
 // the tile's not) form their AT sums from the extrapolated values when they need them.  Without SUB
 // every column whose face is delayed uses masked operands and AT sums fetched a plane ahead.
-template <typename T, int BX, int BY, bool PUB, bool AT, bool SUB>
+// AB2: the Adams-Bashforth update Q + rk_b dQ + c_prev dQ_prev in place of the Runge-Kutta one.
+template <typename T, int BX, int BY, bool PUB, bool AT, bool SUB, bool AB2 = false>
 __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, const int bkx, const int bky,
                                            const int bkz, const uint32_t blk) {
   constexpr bool kMask = AT && !SUB, kSub = AT && SUB;
@@ -737,7 +739,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       if (fin) {
   #pragma unroll
         for (int c = 0; c < 5; ++c) fq[c] = qin[c * N + fi];
-        if (mode == kModeStep && a.rk_a != T(0)) {
+        if (mode == kModeStep && (AB2 || a.rk_a != T(0))) {
   #pragma unroll
           for (int c = 0; c < 5; ++c) fd[c] = __builtin_nontemporal_load(a.dq + c * N + fi);
         }
@@ -913,8 +915,15 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
           // the register and the new state are not read again in this stage: streaming stores
           // keep the L2 for the halo planes
           if (a.store_dq) __builtin_nontemporal_store(d, a.dq + c * N + fi);
-          __builtin_nontemporal_store(fq[c] + a.rk_b * d, a.q_out + c * N + fi);
-          s_tsum[c][tid] += (double)d;
+          if constexpr (AB2) {
+            // Adams-Bashforth (Sec. 2.2, Eq. time_ab): d = dt f^n, the register dt f^{n-1}
+            const T inc = a.rk_b * d + a.c_prev * fd[c];
+            __builtin_nontemporal_store(fq[c] + inc, a.q_out + c * N + fi);
+            s_tsum[c][tid] += (double)inc;
+          } else {
+            __builtin_nontemporal_store(fq[c] + a.rk_b * d, a.q_out + c * N + fi);
+            s_tsum[c][tid] += (double)d;
+          }
         }
       }
     }
@@ -991,7 +1000,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
     }
     __syncthreads();
   }
-  if (tid < kNQ) a.tot_part[blk * kNQ + tid] += (double)a.rk_b * s_tsum[tid][0] * a.vol;
+  if (tid < kNQ) a.tot_part[blk * kNQ + tid] += (double)(AB2 ? T(1) : a.rk_b) * s_tsum[tid][0] * a.vol;
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (dispatch index w goes to XCD w mod 8), and
@@ -1005,12 +1014,12 @@ __device__ __forceinline__ uint32_t xcd_major(uint32_t w, uint32_t nb) {
 }
 
 // MINW: waves per SIMD the register allocation must allow (occupancy target).
-template <typename T, int BX, int BY, int MINW, bool PUB, bool AT, bool SUB>
+template <typename T, int BX, int BY, int MINW, bool PUB, bool AT, bool SUB, bool AB2 = false>
 __global__ __launch_bounds__((Tile<BX, BY>::NT), MINW) void k_stage(FArgs<T> a, int mode) {
   const uint32_t gx = (uint32_t)a.gbx, gxy = gx * (uint32_t)a.gby;
   const uint32_t L = xcd_major(blockIdx.x, gridDim.x);
   const uint32_t bz = L / gxy, r = L - bz * gxy, by = r / gx, bx = r - by * gx;
-  stage_body<T, BX, BY, PUB, AT, SUB>(a, mode, (int)bx, (int)by, (int)bz, L);
+  stage_body<T, BX, BY, PUB, AT, SUB, AB2>(a, mode, (int)bx, (int)by, (int)bz, L);
 }
 
 // Batched stage: one launch over the workgroups of many runs.  work[b] = (run, local workgroup);
@@ -1085,6 +1094,7 @@ FArgs<T> pack(const StageArgs<T>& s, int zchunk) {
   a.mu_exp = s.cf.mu_exp;
   a.rk_a = s.rk_a;
   a.rk_b = s.rk_b;
+  a.c_prev = s.c_prev;
   a.dt = s.dt;
   a.vol = s.vol;
   return a;
@@ -1141,7 +1151,15 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
     const dim3 grid(gx * gy * gz), block(Tile<BX, BY>::NT);
     constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T>(MINW);
     const bool sub = at && s.at_ghost;
-    if (s.publish && sub)
+    if (s.c_prev != T(0)) {  // an Adams-Bashforth step with a stored register (always publishes)
+      if (!s.publish || mode != kModeStep) return hipErrorInvalidValue;
+      if (sub)
+        hipLaunchKernelGGL((k_stage<T, BX, BY, MS, true, true, true, true>), grid, block, dyn, stream, a, mode);
+      else if (at)
+        hipLaunchKernelGGL((k_stage<T, BX, BY, MP, true, true, false, true>), grid, block, dyn, stream, a, mode);
+      else
+        hipLaunchKernelGGL((k_stage<T, BX, BY, MINW, true, false, false, true>), grid, block, dyn, stream, a, mode);
+    } else if (s.publish && sub)
       hipLaunchKernelGGL((k_stage<T, BX, BY, MS, true, true, true>), grid, block, dyn, stream, a, mode);
     else if (s.publish && at)
       hipLaunchKernelGGL((k_stage<T, BX, BY, MP, true, true, false>), grid, block, dyn, stream, a, mode);

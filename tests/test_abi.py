@@ -85,6 +85,7 @@ def test_workspace_checks_without_gpu(lib):
 
 def test_null_handle_calls(lib):
     assert lib.at_rk_step(None, 1) == atns.AT_E_INVAL
+    assert lib.at_ab2_step(None, 1) == atns.AT_E_INVAL
     assert lib.at_set_stage_tuning(None, 1, 64, 5, 64) == atns.AT_E_INVAL
     assert lib.at_batch_set_stage_tuning(None, 1, 64, 5, 64) == atns.AT_E_INVAL
     v = [C.c_int32() for _ in range(4)]

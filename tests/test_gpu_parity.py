@@ -233,6 +233,35 @@ def test_halo_substitution_every_tile_shape():
     assert np.array_equal(run("fp64", 3), f64)
 
 
+@pytest.mark.parametrize("tile", [5, 3])
+def test_ab2_matches_oracle(tile):
+    """Second-order Adams-Bashforth (Sec. 2.2, Eq. time_ab) under CAA delays: one RHS per step at
+    t_n, level n published, the register carrying dt f^{n-1}; after Runge-Kutta steps the next AB2
+    step is forward Euler, as in the oracle.  PEs of 16 x 24 x 16: tile 5 (16x8) puts the
+    extrapolated values in the halo, tile 3 (32x4) uses masked operands.  FP64 fields and statistics
+    match the oracle (relative 1e-12), FP32 fields within the FP32 bound (2e-6)."""
+    n, p = (48, 48, 32), (3, 2, 2)
+    say(f"case ab2 48x48x32 on 3x2x2 PEs, CAA L=3, tile {tile}")
+    q = history_levels(n, 1, 2718)[0]
+    g, o = pair(n, p, q)
+    schedule(g, o, atns.CAA, L=3, c_r=4, n_steps=14)
+    g.set_tuning(tile, 8)
+    h = atns.Sim(atns.Config(n=n, p=p, dt=W.default_dt(q), mu_ref=W.default_mu(n[0]), max_delay=3,
+                             precision="fp32"))
+    h.set_tuning(tile, 8)
+    h.init_field(q)
+    h.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=14)
+    for kind, k in (("rk", 2), ("ab2", 5), ("rk", 1), ("ab2", 3)):
+        for s in (g, o, h):
+            (s.rk_step if kind == "rk" else s.ab2_step)(k)
+        compare_stats(g.stats(), o.stats(), TOL64)
+        ref = o.field()
+        compare_fields(g.get_field(), ref, TOL64, f"fp64 after {kind} x{k}")
+        compare_fields(h.get_field(), ref, 2e-6, f"fp32 after {kind} x{k}")
+    assert g.stats()["step"] == 11
+    h.close()
+
+
 def test_tile_shapes_agree_on_wide_pes():
     """PEs of 48 x 24 x 16: the 16x8 tile has workgroups whose columns and halos all lie inside one
     PE along x and y (no x/y stencil of theirs crosses a face) next to workgroups at the faces; a
