@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-run workload")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the served request trace")
+    ap.add_argument("--no-ab2", action="store_true", help="skip the Adams-Bashforth steps after the timed RK3 steps")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the Poisson arrival window")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON lines)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -102,6 +103,23 @@ def time_steps(torch, sim, warmup, steps):
 
 
 STAGE_KERNELS = ("k_stage", "k_at_sums")
+
+
+def time_ab2(torch, sim, warmup, steps):
+    """Second-order Adams-Bashforth steps (one fused stage each) on the same run, after `warmup`
+    of them (the first is forward Euler); returns ms and the per-kernel event times."""
+    sim.ab2_step(warmup)
+    torch.cuda.synchronize()
+    sim.set_kernel_timing(True)
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    sim.ab2_step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    kt = sim.kernel_timing()
+    sim.set_kernel_timing(False)
+    return t0.elapsed_time(t1), kt
 
 
 def roofline(kt, n, pe, word, pd, steps):
@@ -292,7 +310,8 @@ def main():
     from paper_2003_10561_amd import atns, traffic, workload as W
 
     n, pe, K, Wm = args.n, args.pe, args.steps, args.warmup
-    total = Wm + K + 2
+    AB2_WARM = 2
+    total = Wm + K + 2 + AB2_WARM + K  # then the Adams-Bashforth steps on the same run
     t = time.perf_counter()
     q = W.make_field(n, 3, 0.3, log=log)
     dt, mu = W.default_dt(q), W.default_mu(n)
@@ -310,6 +329,9 @@ def main():
     log(f"fp32 simulation initialised (launch {launch32}); timing")
     ms32, kt32 = time_steps(torch, sim, Wm, K)
     st32 = sim.stats()
+    if not args.no_ab2:
+        ms_ab2, kt_ab2 = time_ab2(torch, sim, AB2_WARM, K)
+        st_ab2 = sim.stats()
     del sim
     torch.cuda.empty_cache()
     log(f"fp32: {ms32 / K:.3f} ms/step; tuning {args.tile, args.zchunk}; kernels {kt32}")
@@ -327,6 +349,14 @@ def main():
            "roofline": rf,
            "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 4) * value / 1e9,
            "stats_after": {k: st32[k] for k in ("K", "eps", "enstrophy", "Mt", "nonfinite")}}
+    if not args.no_ab2:
+        # the paper's own integrator (Sec. 2.2, Eq. time_ab): one RHS per step; not the headline
+        out["ab2"] = {"value": n ** 3 * K / (ms_ab2 * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms_ab2 / K,
+                       "steps": K, "warmup": AB2_WARM,
+                       "stage_ms": sum(kt_ab2[k][0] for k in kt_ab2 if k in STAGE_KERNELS) / K,
+                       "delayed_fraction": traffic.delayed_fraction(sched[Wm + K + AB2_WARM:Wm + 2 * K + AB2_WARM]),
+                       "nonfinite": st_ab2["nonfinite"],
+                       "workload": "the same run continued with second-order Adams-Bashforth steps"}
     if not args.no_fp64:
         sim, _ = build_sim(atns, W, n, pe, "fp64", total, q, dt, mu, fh, args.tile, args.zchunk, not args.no_autotune)
         launch64 = dict(zip(("tile", "zchunk", "tile_delayed", "zchunk_delayed"), sim.get_stage_tuning()))
