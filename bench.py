@@ -351,10 +351,15 @@ def main():
            "stats_after": {k: st32[k] for k in ("K", "eps", "enstrophy", "Mt", "nonfinite")}}
     if not args.no_ab2:
         # the paper's own integrator (Sec. 2.2, Eq. time_ab): one RHS per step; not the headline
+        pd_ab2 = traffic.delayed_fraction(sched[Wm + K + AB2_WARM:Wm + 2 * K + AB2_WARM])
+        stage_ab2 = sum(kt_ab2[k][0] for k in kt_ab2 if k in STAGE_KERNELS) / K
+        gbs_ab2 = traffic.ab2_words_per_point_step((n,) * 3, (pe,) * 3, pd_ab2) * 4 * n ** 3 / (stage_ab2 * 1e-3) / 1e9
         out["ab2"] = {"value": n ** 3 * K / (ms_ab2 * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms_ab2 / K,
-                       "steps": K, "warmup": AB2_WARM,
-                       "stage_ms": sum(kt_ab2[k][0] for k in kt_ab2 if k in STAGE_KERNELS) / K,
-                       "delayed_fraction": traffic.delayed_fraction(sched[Wm + K + AB2_WARM:Wm + 2 * K + AB2_WARM]),
+                       "steps": K, "warmup": AB2_WARM, "stage_ms": stage_ab2, "delayed_fraction": pd_ab2,
+                       "roofline": {"bound": "hbm", "achieved": gbs_ab2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": gbs_ab2 / HBM_PEAK_GBS,
+                                    "algorithmic_bytes_per_point_step":
+                                        4 * traffic.ab2_words_per_point_step((n,) * 3, (pe,) * 3, pd_ab2)},
                        "nonfinite": st_ab2["nonfinite"],
                        "workload": "the same run continued with second-order Adams-Bashforth steps"}
     if not args.no_fp64:

@@ -25,6 +25,14 @@ def bytes_per_point_step(n, p, p_delayed: float, word: int) -> float:
     return word * words_per_point_step(n, p, p_delayed)
 
 
+def ab2_words_per_point_step(n, p, p_delayed: float) -> float:
+    """Second-order Adams-Bashforth (Sec. 2.2, Eq. time_ab): one stage per step reads Q and the
+    stored dt f^{n-1} and writes Q and dt f^n (20 words), publishes the face layers (9 phi) and, on
+    delayed faces, reads 3 levels of the 9 ghost words once (27 phi p_d)."""
+    phi = ghost_fraction(n, p)
+    return 20.0 + 9.0 * phi + 27.0 * phi * p_delayed
+
+
 def delayed_fraction(table) -> float:
     """Fraction of (step, PE, face) entries with delay >= 1 in an int8 schedule table."""
     import numpy as np
