@@ -242,9 +242,9 @@ hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode, bool at) {
 }
 
 template <typename T>
-hipError_t launch_views(at_sim* s, const StageArgs<T>& a) {
+hipError_t launch_views(at_sim* s, const StageArgs<T>& a, int nst = 3) {
   if (s->timer) s->timer->before(kKGhost, s->stream);
-  hipError_t e = launch_at_sums<T>(a, kRkC, s->stream);
+  hipError_t e = launch_at_sums<T>(a, kRkC, s->stream, nst);
   if (s->timer) s->timer->after(kKGhost, s->stream);
   return e;
 }
@@ -358,7 +358,7 @@ int do_ab2_steps(at_sim* s, int nsteps) {
     a.c_prev = s->ab2_prev ? T(-0.5) : T(0);
     a.publish = 1;
     a.store_dq = 1;
-    if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a));
+    if (s->step_delayed[(size_t)s->step]) HIP_TRY(launch_views<T>(s, a, 1));  // the c_s = 0 sums only
     HIP_TRY(launch_hooked<T>(s, a, kModeStepH, s->step_delayed[(size_t)s->step] != 0));
     s->qcur = 1 - s->qcur;
     s->ab2_prev = 1;

@@ -109,7 +109,8 @@ size_t fused_lds_bytes(int tile, size_t word, bool forced);
 template <typename T>
 hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, bool at, hipStream_t stream);
 template <typename T>
-hipError_t launch_at_sums(const StageArgs<T>& a, const double* cs, hipStream_t stream);  // cs: c_s of stages 1-3
+// cs: c_s of stages 1-3; nst: the stages written (3, or 1 for an Adams-Bashforth step: c_s = cs[0])
+hipError_t launch_at_sums(const StageArgs<T>& a, const double* cs, hipStream_t stream, int nst = 3);
 
 // Batched launches (one launch over the workgroups of many runs).  A run table is an array of
 // batch_arg_bytes<T>() records written by pack_batch_arg; work lists hold (run, local block).

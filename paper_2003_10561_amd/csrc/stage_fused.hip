@@ -1184,14 +1184,16 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
 // ring components, sum_m a_m (extrapolated value at X + m) at the reader's own ring offset, with
 // a = (1, -8, 8, -1) the stencil numerators.  The delays and levels are those of the step, the
 // same for its three stages, which differ only in c_s: one launch per step reads the levels once
-// and writes the sums of stage s into the s-th of three consecutive slot-sized regions of gv.
+// and writes the sums of stage s into the s-th of three consecutive slot-sized regions of gv (an
+// Adams-Bashforth step writes only the first, c_s = 0).
 // One thread serves the two readers of a face (layers 0, 1 or 2, 3), which share their delay and
 // the source points across it (each extrapolated once).  Readers whose face has k = 0 are not
 // written.  For a run whose stages run on tiles aligned with its PEs (at_ghost), the x and y
 // entries hold the two extrapolated values instead (layers -2, -1 at the slots of readers 0, 1;
 // layers e, e+1 at those of readers 2, 3), which the stage kernel places in its halo; the sums are
 // formed from them as at_sum_of does.
-template <typename T>
+// NST: the stages whose sums are written (3 for Runge-Kutta; 1, c_s = 0, for Adams-Bashforth).
+template <typename T, int NST = 3>
 __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ gv, const uint32_t tid,
                                              const T c0, const T c1, const T c2) {
   const uint32_t h0 = a.slab0 / 2, h1 = a.slab1 / 2, h2 = a.slab2 / 2;
@@ -1244,7 +1246,7 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
   const bool ghost = a.at_ghost != 0 && d < 2;
   T w[3][3];
 #pragma unroll
-  for (int st = 0; st < 3; ++st) {
+  for (int st = 0; st < NST; ++st) {
     const T kap = T(k) + (st == 0 ? c0 : st == 1 ? c1 : c2);
     w[st][0] = (kap + T(1)) * (kap + T(2)) * T(0.5);
     w[st][1] = -kap * (kap + T(2));
@@ -1267,7 +1269,7 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
     const uint32_t oa = srcA + (uint32_t)c * ss, ob = srcB + (uint32_t)c * ss;
     const T a0 = r0[oa], a1 = r1[oa], a2 = r2[oa], b0 = r0[ob], b1 = r1[ob], b2 = r2[ob];
 #pragma unroll
-    for (int st = 0; st < 3; ++st) {
+    for (int st = 0; st < NST; ++st) {
       const T va = w[st][0] * a0 + w[st][1] * a1 + w[st][2] * a2;
       const T vb = w[st][0] * b0 + w[st][1] * b1 + w[st][2] * b2;
       // lower face: reader 0 = 1 va - 8 vb (offsets -2, -1), reader 1 = 1 vb (offset -2);
@@ -1282,9 +1284,9 @@ __device__ __forceinline__ void at_sums_body(const FArgs<T>& a, T* __restrict__ 
   }
 }
 
-template <typename T>
+template <typename T, int NST>
 __global__ __launch_bounds__(256) void k_at_sums(FArgs<T> a, T* __restrict__ gv, T c0, T c1, T c2) {
-  at_sums_body<T>(a, gv, blockIdx.x * 256u + threadIdx.x, c0, c1, c2);
+  at_sums_body<T, NST>(a, gv, blockIdx.x * 256u + threadIdx.x, c0, c1, c2);
 }
 
 // Batched sums: work[b] = (run, local block of 256 reader pairs); runs that read no delayed level
@@ -1302,15 +1304,19 @@ __global__ __launch_bounds__(256) void k_at_sums_batch(const FArgs<T>* __restric
 }  // namespace
 
 template <typename T>
-hipError_t launch_at_sums(const StageArgs<T>& a, const double* cs, hipStream_t stream) {
+hipError_t launch_at_sums(const StageArgs<T>& a, const double* cs, hipStream_t stream, int nst) {
   const Geom& g = a.g;
   const int64_t total = (g.slab[0] + g.slab[1] + g.slab[2]) / 2;  // reader pairs
-  hipLaunchKernelGGL(k_at_sums<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
-                     pack<T>(a, 4), a.gv_out, (T)cs[0], (T)cs[1], (T)cs[2]);
+  if (nst != 1 && nst != 3) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  if (nst == 3)
+    hipLaunchKernelGGL((k_at_sums<T, 3>), grid, block, 0, stream, pack<T>(a, 4), a.gv_out, (T)cs[0], (T)cs[1], (T)cs[2]);
+  else
+    hipLaunchKernelGGL((k_at_sums<T, 1>), grid, block, 0, stream, pack<T>(a, 4), a.gv_out, (T)cs[0], (T)cs[1], (T)cs[2]);
   return hipGetLastError();
 }
-template hipError_t launch_at_sums<double>(const StageArgs<double>&, const double*, hipStream_t);
-template hipError_t launch_at_sums<float>(const StageArgs<float>&, const double*, hipStream_t);
+template hipError_t launch_at_sums<double>(const StageArgs<double>&, const double*, hipStream_t, int);
+template hipError_t launch_at_sums<float>(const StageArgs<float>&, const double*, hipStream_t, int);
 
 int64_t fused_blocks(const Geom& g, int tile, int zchunk) {
   const int bx = tile_bx(tile), by = tile_by(tile);
