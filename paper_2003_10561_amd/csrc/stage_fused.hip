@@ -547,7 +547,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   constexpr bool kHv = kSub && !PUB;
   __shared__ T s_hv[kHv ? 4 : 1][kHv ? TL::NY2 + TL::NX2 : 1];
   const bool hx = kHv && (role == 1 || role == 2) && near_x;
-  const int hslot = kSub ? max(tid - TL::NOWN, 0) : 0;
+  const int hslot = kHv ? max(tid - TL::NOWN, 0) : 0;
   auto hx_fetch = [&](int zpl) {
     const uint32_t o = (uint32_t)pmod(zpl, nz) * zsx + opx - (uint32_t)(lxe < 2 ? lxe : lxe - a.ex + 2);
 #pragma unroll
@@ -1118,10 +1118,13 @@ constexpr int pub_at_waves(int ma) {
 }
 
 // Occupancy target of the instantiations for aligned tiles (SUB): in FP32 they fit the registers of
-// 4 waves per SIMD (the publishing one with 2 or 3 spilled), whatever the tile's own target.
-template <typename T>
+// 4 waves per SIMD (the publishing one with 2 or 3 spilled), whatever the tile's own target; a
+// workgroup shape that keeps as many workgroups per CU (16 wave slots) at 3 waves per SIMD as at 4
+// (6- and 9-wave workgroups) targets 3.
+template <typename T, int BX, int BY>
 constexpr int sub_waves(int minw) {
-  return sizeof(T) == 4 ? 4 : minw;
+  constexpr int nw = Tile<BX, BY>::NT / 64;
+  return sizeof(T) != 4 ? minw : (12 / nw == 16 / nw ? 3 : 4);
 }
 
 // Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950); the halo AT-sum
@@ -1149,7 +1152,7 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
     a.gby = (int)gy;
     const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid(gx * gy * gz), block(Tile<BX, BY>::NT);
-    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T>(MINW);
+    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T, BX, BY>(MINW);
     const bool sub = at && s.at_ghost;
     if (s.c_prev != T(0)) {  // an Adams-Bashforth step with a stored register (always publishes)
       if (!s.publish || mode != kModeStep) return hipErrorInvalidValue;
@@ -1388,7 +1391,7 @@ hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, b
     const size_t dyn = forced ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid((unsigned)nblk), block(Tile<BX, BY>::NT);
     const FArgs<T>* r = (const FArgs<T>*)runs;
-    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T>(MINW);
+    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T, BX, BY>(MINW);
     if (at == 0) {
       if (publish)
         hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, false, false>), grid, block, dyn, stream, r, work, mode);
