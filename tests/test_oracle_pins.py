@@ -628,3 +628,94 @@ def test_stage_time_extrapolation_order():
             runs.append(o.field())
         diffs.append(np.abs(runs[0] - runs[1]).max())
     assert math.log2(diffs[0] / diffs[1]) > 2.5, diffs
+
+
+# ------------------------------------------------------------------ forcing source (Sec. 4.2)
+def _single_mode_forcing(n_steps):
+    """Forcing tables whose rows hold one or two wavevectors each, so that every row's field is a
+    known closed form: a real amplitude a at k gives 2 a cos(k.x), an imaginary one b gives
+    -2 b sin(k.x).  Row 0: f_y = cos(x), f_x = -0.5 sin(z).  Row 1: f_z = cos(y) + 0.25 cos(x + y).
+    Row 2 (and later): f_x = 0.75 cos(2 y).  Each amplitude is normal to its k (solenoidal)."""
+    ks = [tuple(k) for k in W.forcing_wavevectors().tolist()]
+    fh = np.zeros((n_steps, 40, 3, 2))
+    fh[0, ks.index((1, 0, 0)), 1, 0] = 0.5
+    fh[0, ks.index((0, 0, 1)), 0, 1] = 0.25
+    fh[1, ks.index((0, 1, 0)), 2, 0] = 0.5
+    fh[1, ks.index((1, 1, 0)), 2, 0] = 0.125
+    fh[2:, ks.index((0, 2, 0)), 0, 0] = 0.375
+    return fh
+
+
+def _closed_form_force(row, n):
+    X, Y, Z = F.grid(n)
+    z = np.zeros_like(X)
+    if row == 0:
+        return np.stack([-0.5 * np.sin(Z), np.cos(X), z])
+    if row == 1:
+        return np.stack([z, z, np.cos(Y) + 0.25 * np.cos(X + Y)])
+    return np.stack([0.75 * np.cos(2 * Y), z, z])
+
+
+def _uniform_forced_state(n, rho=2.0, vel=(0.25, -0.5, 0.125), T=1.5, gamma=1.5):
+    """rho, u, T constant: every flux is the same number at every point, so the flux divergence
+    vanishes and the RHS is the forcing source alone.  gamma = 1.5 makes c_v = 2 exact."""
+    cv = 1.0 / (gamma - 1.0)
+    ke = 0.5 * sum(v * v for v in vel)
+    q = np.empty((5,) + (n[2], n[1], n[0]))
+    q[0] = rho
+    for a in range(3):
+        q[1 + a] = rho * vel[a]
+    q[4] = rho * (cv * T + ke)
+    return q
+
+
+def test_forcing_source_on_uniform_state_two_steps():
+    """Eq. mome carries rho f_i (Sec. 4.2); in total-energy form the energy equation gains its work
+    rho f.u.  On a uniform state with constant velocity the RHS is therefore exactly
+    (0, rho f, rho f.u) with f the closed form of the current step's forcing row.  Checked at step
+    0 (one supplied level) and step 1 (two supplied levels), whose rows differ: a wrong sign, a
+    missing or wrong energy term, a permuted component or the wrong row fails."""
+    n = (16, 12, 8)
+    q = _uniform_forced_state(n)
+    rho, m = 2.0, (0.5, -1.0, 0.25)
+    fh = _single_mode_forcing(4)
+    for nlev, row in ((1, 0), (2, 1)):
+        o = Oracle(cfg_for(n, (2, 3, 1), dt=1e-3, mu=0.01, gamma=1.5, forcing=True))
+        o.init_field(np.stack([q] * nlev) if nlev > 1 else q, nlev)
+        o.set_schedule(SYNC, n_steps=4)
+        o.set_forcing(fh)
+        r = o.rhs()
+        f = _closed_form_force(row, n)
+        assert np.abs(r[0]).max() == 0.0
+        for a in range(3):
+            np.testing.assert_allclose(r[1 + a], rho * f[a], rtol=0, atol=1e-14)
+        np.testing.assert_allclose(r[4], m[0] * f[0] + m[1] * f[1] + m[2] * f[2], rtol=0, atol=1e-14)
+        # the other rows' fields really differ from this one (so the row choice is tested)
+        for other in (0, 1, 2):
+            if other != row:
+                assert np.abs(_closed_form_force(other, n) - f).max() > 0.5
+
+
+def test_forcing_held_fixed_within_step():
+    """The force is held fixed over the three stages of a step (reading A16).  From a uniform state
+    one RK3 step gives Q + dt (0, rho f_n, rho f_n.u) + O(dt^2): the error against that falls four
+    times when dt halves.  Evaluating a later stage with the next row (which differs here) would
+    leave an O(dt) error, a ratio near 2."""
+    n = (16, 16, 8)
+    q = _uniform_forced_state(n)
+    fh = _single_mode_forcing(4)
+    f1 = _closed_form_force(1, n)
+    src = np.stack([np.zeros_like(f1[0]), 2.0 * f1[0], 2.0 * f1[1], 2.0 * f1[2],
+                    0.5 * f1[0] - 1.0 * f1[1] + 0.25 * f1[2]])
+    errs = []
+    for dt in (2e-3, 1e-3):
+        o = Oracle(cfg_for(n, (2, 2, 1), dt=dt, mu=0.01, gamma=1.5, forcing=True))
+        o.init_field(np.stack([q, q]), 2)  # current step 1: row 1
+        o.set_schedule(SYNC, n_steps=4)
+        o.set_forcing(fh)
+        o.rk_step(1)
+        errs.append(np.abs(o.field() - (q + dt * src)).max())
+    ratio = errs[0] / errs[1]
+    assert 3.6 < ratio < 4.4, errs
+    # and the step moved the state by dt * source to leading order
+    assert errs[1] < 1e-3 * 1e-3 * np.abs(src).max(), errs
