@@ -46,7 +46,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the same workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-cfg2", action="store_true", help="skip the decaying 256^3 FP64 configuration")
+    ap.add_argument("--cfg2-steps", type=int, default=100)
     ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
     ap.add_argument("--zchunk", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="library default launch shape for the 512^3 runs")
@@ -85,10 +87,11 @@ def build_sim(atns, W, n, pe, precision, n_steps_total, q, dt, mu, fh, tile=None
     return sim, tuned
 
 
-def time_steps(torch, sim, warmup, steps):
-    sim.rk_step(warmup)
-    torch.cuda.synchronize()
-    sim.set_kernel_timing(True)
+def time_window(torch, sim, steps, warmup=0):
+    """`warmup` untimed steps, then `steps` RK3 steps between two HIP events on the launch stream
+    (torch's current stream, which the library enqueues on); no per-kernel events inside."""
+    if warmup:
+        sim.rk_step(warmup)
     stream = torch.cuda.current_stream()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -96,25 +99,18 @@ def time_steps(torch, sim, warmup, steps):
     sim.rk_step(steps)
     t1.record(stream)
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    kt = sim.kernel_timing()
-    sim.set_kernel_timing(False)
-    return ms, kt
+    return t0.elapsed_time(t1)
 
 
-STAGE_KERNELS = ("k_stage", "k_at_sums")
-
-
-def time_ab2(torch, sim, warmup, steps):
-    """Second-order Adams-Bashforth steps (one fused stage each) on the same run, after `warmup`
-    of them (the first is forward Euler); returns ms and the per-kernel event times."""
-    sim.ab2_step(warmup)
-    torch.cuda.synchronize()
+def kernel_window(torch, sim, steps, step_fn=None):
+    """The next `steps` steps with every kernel bracketed by HIP events on the launch stream: the
+    per-kernel durations the roofline divides by.  Returns (window ms, {kernel: (ms, launches)})."""
     sim.set_kernel_timing(True)
     stream = torch.cuda.current_stream()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0.record(stream)
-    sim.ab2_step(steps)
+    (step_fn or sim.rk_step)(steps)
     t1.record(stream)
     torch.cuda.synchronize()
     kt = sim.kernel_timing()
@@ -122,10 +118,14 @@ def time_ab2(torch, sim, warmup, steps):
     return t0.elapsed_time(t1), kt
 
 
+STAGE_KERNELS = ("k_stage", "k_at_sums")
+
+
 def roofline(kt, n, pe, word, pd, steps):
-    """Dominant launch = one RK stage: the fused stage kernel plus, at delayed stages, the AT face
-    views it reads (the method's delayed-level reads).  Algorithmic bytes per stage launch over
-    the average event-timed duration of those kernels per stage."""
+    """Dominant launch = one RK stage: the fused stage kernel plus, at delayed steps, the AT sums it
+    reads (the method's delayed-level reads).  Algorithmic bytes per stage launch (the minimal count
+    of traffic.words_per_point_step, a third of a step's) over the average event-timed duration of
+    those kernels per stage."""
     from paper_2003_10561_amd import traffic
     stage_kernels = [k for k in kt if k in STAGE_KERNELS]
     launches = steps * 3
@@ -134,10 +134,13 @@ def roofline(kt, n, pe, word, pd, steps):
     bytes_per_launch = words * word * n ** 3
     achieved = bytes_per_launch / (stage_ms * 1e-3) / 1e9
     name = "+".join(stage_kernels)
+    loose = traffic.words_per_point_step_stage_reads((n,) * 3, (pe,) * 3, pd) * word
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": stage_ms,
-            "algorithmic_bytes_per_point_step": words * 3 * word}
+            "algorithmic_bytes_per_point_step": words * 3 * word,
+            "bytes_per_point_step_stage_reads": loose,
+            "frac_stage_reads": loose / 3.0 * n ** 3 / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def stage_source_sha():
@@ -276,24 +279,120 @@ def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64, tile_delayed=-
                         "FP32, continuous batching"}
 
 
-def cpu_baseline(W, n, steps):
-    """The CPU FP64 oracle on a bounded sample with the same PE shape (64^3), delays and forcing."""
+def _oracle_threads(n):
+    """Set the OpenMP thread count of the oracle's runtime (its library links libgomp)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def _oracle_rate(W, n, pe, steps, mode, L, seed, field_seed, forcing, reps):
+    """pt-steps/s of the oracle over `steps` RK3 steps after initialisation (not timed); median of
+    `reps` runs."""
     from oracle import Oracle, OracleConfig
-    pe = max(1, n // 64)
-    q = W.make_field(n, 3, 0.3)
+    q = W.make_field(n, field_seed, 0.3)
     dt, mu = W.default_dt(q), W.default_mu(n)
-    fh = W.make_forcing(303, steps + 2, dt, 1.0, 0.1 * W.urms_of(q))
-    o = Oracle(OracleConfig(n=(n, n, n), p=(pe, pe, pe), dt=dt, mu_ref=mu, max_delay=3, forcing=True))
-    o.init_field(q)
-    o.set_schedule(1, L=3, c_r=4, n_steps=steps + 2)
-    o.set_forcing(fh)
-    t = time.perf_counter()
-    o.rk_step(steps)
-    el = time.perf_counter() - t
+    fh = W.make_forcing(303, steps + 2, dt, 1.0, 0.1 * W.urms_of(q)) if forcing else None
+    rates, secs = [], []
+    for _ in range(reps):
+        o = Oracle(OracleConfig(n=(n, n, n), p=pe, dt=dt, mu_ref=mu, max_delay=max(L, 1), forcing=forcing))
+        o.init_field(q)
+        if mode == "caa":
+            o.set_schedule(1, L=L, c_r=L + 1, n_steps=steps + 2)
+        else:
+            o.set_schedule(2, L=L, seed=seed, n_steps=steps + 2)
+        if forcing:
+            o.set_forcing(fh)
+        t = time.perf_counter()
+        o.rk_step(steps)
+        el = time.perf_counter() - t
+        o.close()
+        secs.append(el)
+        rates.append(n ** 3 * steps / el)
+    return float(np.median(rates)), float(np.median(secs))
+
+
+def cpu_baseline(W, n, steps):
+    """The CPU FP64 oracle on the host's cores, timed as the baseline protocol asks: median of 3 runs
+    with initialisation excluded.  `value` is a 128^3 sample with the headline's PE shape (64^3),
+    delays and forcing; beside it the 32^3 plain-method configuration in full, a few steps of the
+    256^3 decaying configuration, and the 1-thread rate of the 128^3 sample (fewer steps)."""
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n ** 3 * steps / el, "unit": "grid-pt-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n}^3, {pe}x{pe}x{pe} PEs of 64^3, CAA L=3, forced, FP64, {steps} RK3 steps "
-                      f"({el:.1f} s)"}
+    pe = max(1, n // 64)
+    v, el = _oracle_rate(W, n, (pe,) * 3, steps, "caa", 3, 0, 3, True, 3)
+    cfg1, el1 = _oracle_rate(W, 32, (2, 2, 1), 10, "caa", 3, 0, 1, False, 3)
+    cfg2, el2 = _oracle_rate(W, 256, (4, 4, 4), 7, "saa", 2, 102, 2, False, 1)
+    _oracle_threads(1)
+    one, el_one = _oracle_rate(W, n, (pe,) * 3, 2, "caa", 3, 0, 3, True, 1)
+    _oracle_threads(cores)
+    return {"value": v, "unit": "grid-pt-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n}^3, {pe}x{pe}x{pe} PEs of 64^3, CAA L=3, forced, FP64, {steps} RK3 steps, median of 3 "
+                      f"({el:.1f} s each)",
+            "cfg1_full": {"value": cfg1, "sample": "32^3, 2x2x1 PEs, CAA L=3, FP64, 10 RK3 steps (the whole "
+                                                   f"configuration), median of 3 ({el1:.2f} s each)"},
+            "cfg2_sample": {"value": cfg2, "sample": f"256^3, 4x4x4 PEs, SAA L=2 seed 102, FP64, first 7 of its "
+                                                     f"100 RK3 steps ({el2:.1f} s)"},
+            "one_thread": {"value": one, "cores": 1, "sample": f"{n}^3 as value, 2 RK3 steps ({el_one:.1f} s)"}}
+
+
+def field_rel_l2(a, b):
+    """Relative L2 error of each conserved component of a against b."""
+    return [float(np.linalg.norm((a[c] - b[c]).ravel()) / np.linalg.norm(b[c].ravel())) for c in range(a.shape[0])]
+
+
+def decaying_cfg2(torch, atns, W, traffic, steps):
+    """The decaying-turbulence configuration: FP64, 256^3 on 4x4x4 PEs of 64^3, random (SAA) delays
+    uniform in {0, 1, 2} from seed 102 after the L + 3 = 5 synchronous warm-up steps, seeded field 2,
+    statistics read back after every step.  Pass 1 times the steps with their statistics (no
+    per-kernel events); pass 2 repeats them from the same initial field with kernel events, for
+    the roofline of the stage kernels and the cost of the statistics."""
+    n, pe, L = 256, 4, 2
+    q = W.make_field(n, 2, 0.3)
+    dt, mu = W.default_dt(q), W.default_mu(n)
+    cfg = atns.Config(n=(n,) * 3, p=(pe,) * 3, dt=dt, mu_ref=mu, max_delay=L, precision="fp64")
+    sim = atns.Sim(cfg)
+    sim.init_field(q)
+    sim.set_delay_schedule(atns.SAA, L=L, seed=102, n_steps=steps + 1)
+    b = atns.Batch("fp64")
+    b.add(sim)
+    b.autotune(None, reps=2)
+    shapes = b.get_stage_tuning()
+    b.remove(sim)
+    b.close()
+    sim.set_stage_tuning(*shapes)
+
+    def run(with_events):
+        sim.init_field(q)
+        if with_events:
+            sim.set_kernel_timing(True)
+        stream = torch.cuda.current_stream()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        last = None
+        for _ in range(steps):
+            sim.rk_step(1)
+            last = sim.stats()  # synchronises: the statistics of every step reach the host
+        t1.record(stream)
+        torch.cuda.synchronize()
+        kt = sim.kernel_timing() if with_events else None
+        if with_events:
+            sim.set_kernel_timing(False)
+        return t0.elapsed_time(t1), kt, last
+
+    ms, _, st = run(False)
+    ms_ev, kt, _ = run(True)
+    # delayed fraction: after the warm-up every draw is uniform in {0..L}; its expectation (the
+    # 36k draws of the window match it to about 0.5%)
+    pd = max(0, steps - (L + 3)) / steps * L / (L + 1)
+    rf = roofline(kt, n, pe, 8, pd, steps)
+    sim.close()
+    torch.cuda.empty_cache()
+    return {"value": n ** 3 * steps / (ms * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms / steps,
+            "steps": steps, "launch": dict(zip(("tile", "zchunk", "tile_delayed", "zchunk_delayed"), shapes)),
+            "stats_ms_per_step": kt.get("k_stats", (0.0, 1))[0] / steps, "delayed_fraction": pd,
+            "roofline": rf, "stats_last": {k: st[k] for k in ("step", "K", "eps", "enstrophy", "Mt", "nonfinite")},
+            "workload": "decaying turbulence 256^3, 4x4x4 virtual PEs of 64^3, SAA L=2 seed 102, FP64, "
+                        "statistics every step"}
 
 
 def main():
@@ -311,7 +410,8 @@ def main():
 
     n, pe, K, Wm = args.n, args.pe, args.steps, args.warmup
     AB2_WARM = 2
-    total = Wm + K + 2 + AB2_WARM + K  # then the Adams-Bashforth steps on the same run
+    # warm-up, the timed window, the kernel-event window, then the Adams-Bashforth steps
+    total = Wm + 2 * K + 2 + AB2_WARM + K
     t = time.perf_counter()
     q = W.make_field(n, 3, 0.3, log=log)
     dt, mu = W.default_dt(q), W.default_mu(n)
@@ -322,20 +422,24 @@ def main():
     for s in range(4, total):
         sched[s] = s % 4
     pd = traffic.delayed_fraction(sched[Wm:Wm + K])
+    pd_k = traffic.delayed_fraction(sched[Wm + K:Wm + 2 * K])
 
     sim, tuned = build_sim(atns, W, n, pe, "fp32", total, q, dt, mu, fh, args.tile, args.zchunk, not args.no_autotune)
     launch32 = dict(zip(("tile", "zchunk", "tile_delayed", "zchunk_delayed"), sim.get_stage_tuning()),
                     autotuned=tuned)
     log(f"fp32 simulation initialised (launch {launch32}); timing")
-    ms32, kt32 = time_steps(torch, sim, Wm, K)
+    ms32 = time_window(torch, sim, K, warmup=Wm)
+    ms32_ev, kt32 = kernel_window(torch, sim, K)
     st32 = sim.stats()
+    f32 = sim.get_field() if not args.no_fp64 else None
     if not args.no_ab2:
-        ms_ab2, kt_ab2 = time_ab2(torch, sim, AB2_WARM, K)
+        sim.ab2_step(AB2_WARM)
+        ms_ab2, kt_ab2 = kernel_window(torch, sim, K, sim.ab2_step)
         st_ab2 = sim.stats()
     del sim
     torch.cuda.empty_cache()
-    log(f"fp32: {ms32 / K:.3f} ms/step; tuning {args.tile, args.zchunk}; kernels {kt32}")
-    rf = roofline(kt32, n, pe, 4, pd, K)
+    log(f"fp32: {ms32 / K:.3f} ms/step ({ms32_ev / K:.3f} with kernel events); kernels {kt32}")
+    rf = roofline(kt32, n, pe, 4, pd_k, K)
     rf["traffic"] = measured_traffic(n, pe, "fp32")
     value = n ** 3 * K / (ms32 * 1e-3)
     out = {"metric": METRIC, "value": value, "unit": "grid-pt-steps/s", "n_gpus": 1, "steps": K,
@@ -347,11 +451,14 @@ def main():
                       "n": n, "pe": [pe, pe, pe], "delays": "CAA L=3", "precision": "fp32"},
            "launch": launch32,
            "roofline": rf,
+           "kernel_window": {"steps": K, "ms_per_step": ms32_ev / K, "delayed_fraction": pd_k,
+                             "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in kt32.items()},
+                             "launches": {k: v[1] for k, v in kt32.items()}},
            "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 4) * value / 1e9,
            "stats_after": {k: st32[k] for k in ("K", "eps", "enstrophy", "Mt", "nonfinite")}}
     if not args.no_ab2:
         # the paper's own integrator (Sec. 2.2, Eq. time_ab): one RHS per step; not the headline
-        pd_ab2 = traffic.delayed_fraction(sched[Wm + K + AB2_WARM:Wm + 2 * K + AB2_WARM])
+        pd_ab2 = traffic.delayed_fraction(sched[Wm + 2 * K + AB2_WARM:Wm + 3 * K + AB2_WARM])
         stage_ab2 = sum(kt_ab2[k][0] for k in kt_ab2 if k in STAGE_KERNELS) / K
         gbs_ab2 = traffic.ab2_words_per_point_step((n,) * 3, (pe,) * 3, pd_ab2) * 4 * n ** 3 / (stage_ab2 * 1e-3) / 1e9
         out["ab2"] = {"value": n ** 3 * K / (ms_ab2 * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms_ab2 / K,
@@ -361,24 +468,36 @@ def main():
                                     "algorithmic_bytes_per_point_step":
                                         4 * traffic.ab2_words_per_point_step((n,) * 3, (pe,) * 3, pd_ab2)},
                        "nonfinite": st_ab2["nonfinite"],
-                       "workload": "the same run continued with second-order Adams-Bashforth steps"}
+                       "workload": "the same run continued with second-order Adams-Bashforth steps (timed with "
+                                   "kernel events)"}
     if not args.no_fp64:
         sim, _ = build_sim(atns, W, n, pe, "fp64", total, q, dt, mu, fh, args.tile, args.zchunk, not args.no_autotune)
         launch64 = dict(zip(("tile", "zchunk", "tile_delayed", "zchunk_delayed"), sim.get_stage_tuning()))
         log("fp64 simulation initialised; timing")
-        ms64, kt64 = time_steps(torch, sim, Wm, K)
+        ms64 = time_window(torch, sim, K, warmup=Wm)
+        ms64_ev, kt64 = kernel_window(torch, sim, K)
         st64 = sim.stats()
+        f64 = sim.get_field()
         del sim
         torch.cuda.empty_cache()
         log(f"fp64: {ms64 / K:.3f} ms/step")
         v64 = n ** 3 * K / (ms64 * 1e-3)
-        rf64 = roofline(kt64, n, pe, 8, pd, K)
+        rf64 = roofline(kt64, n, pe, 8, pd_k, K)
+        errs = field_rel_l2(f32, f64)
+        del f32, f64
         out["fp64"] = {"value": v64, "ms_per_step": ms64 / K, "roofline_frac": rf64["frac"], "launch": launch64,
-                       "achieved_gbs": rf64["achieved"],
+                       "achieved_gbs": rf64["achieved"], "avg_launch_ms": rf64["avg_launch_ms"],
                        "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 8) * v64 / 1e9,
                        "fp32_speedup": value / v64,
+                       "fp32_vs_fp64_field_rel_l2": dict(zip(("rho", "rho_u", "rho_v", "rho_w", "E"), errs)),
                        "fp32_vs_fp64_stats_rel": {k: abs(st32[k] - st64[k]) / abs(st64[k])
-                                                  for k in ("K", "eps", "enstrophy", "Mt")}}
+                                                  for k in ("K", "eps", "enstrophy", "Mt")},
+                       "error_note": f"FP32 and FP64 runs after the same {Wm + 2 * K} RK3 steps; the FP64 path "
+                                     "matches the FP64 oracle at this size"}
+    if not args.no_cfg2:
+        log("decaying 256^3 FP64 configuration ...")
+        out["decaying_256"] = decaying_cfg2(torch, atns, W, traffic, args.cfg2_steps)
+        log(f"decaying_256: {out['decaying_256']}")
     if not args.no_batch:
         log("batched 64-run workload ...")
         out["batched"] = batched_workload(torch, atns, W, args.batch_steps, args.batch_steps, args.tune_cache)

@@ -251,9 +251,10 @@ ATNS_API int at_batch_get_stage_tuning(at_batch* batch, int32_t* tile_sync, int3
  * otherwise times, for every feasible (tile, z chunk) (z chunks 8, 16, ..., 512, up to the members'
  * largest n_z), `reps` synchronous trial stages and (if
  * f > 0) `reps` delayed ones (each member at the delays of its first delayed step), keeps the
- * fastest shape of each kind (as at_batch_set_stage_tuning) and appends them to the cache.  A trial rewrites only buffers
- * that are dead between steps (the second state buffer and the RK register) and discards its
- * conserved totals, so the members' states are unchanged.  *best_ms (may be NULL) receives
+ * fastest shape of each kind (as at_batch_set_stage_tuning) and appends them to the cache.  A trial
+ * rewrites only the second state buffer (dead between steps), neither stores the RK register (which
+ * may hold the dt f^{n-1} of Adams-Bashforth steps) nor publishes, and discards its conserved
+ * totals, so the members' states, including a stored Adams-Bashforth register, are unchanged.  *best_ms (may be NULL) receives
  * (1 - f) t_sync + f t_delayed of the chosen shapes.  Synchronises.  Errors: AT_E_STATE (empty batch), AT_E_SCHEDULE,
  * AT_E_INVAL, AT_E_HIP. */
 ATNS_API int at_batch_autotune(at_batch* batch, const char* cache_path, int32_t reps, double* best_ms);

@@ -323,11 +323,11 @@ int64_t first_delayed_step(const at_sim* s) {
   return -1;
 }
 
-// One trial stage (stage 1, no publication, FP64 totals discarded) of every run with the given
-// launch shape: synchronous (every run in the plain instantiation), or delayed (every run that
-// ever reads delayed levels takes the delays of its first such step and the AT instantiation).
-// It rewrites only buffers that hold no live data between steps: the other state buffer and the
-// RK register.
+// One trial stage (stage 1, no publication, no register store, FP64 totals discarded) of every
+// run with the given launch shape: synchronous (every run in the plain instantiation), or delayed
+// (every run that ever reads delayed levels takes the delays of its first such step and the AT
+// instantiation).  It rewrites only the other state buffer, which holds no live data between
+// steps; the RK register is left alone, since after Adams-Bashforth steps it carries dt f^{n-1}.
 template <typename T>
 int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, double* ms) {
   // both kinds of stage in the trial shape; the tables of kind 0 serve both launches
@@ -356,6 +356,7 @@ int trial_stage(at_batch* b, int tile, int zchunk, int reps, bool delayed, doubl
     for (int64_t k = 0; k < nb; ++k) sw[is++] = make_uint2((unsigned)m, (unsigned)k);
     StageArgs<T> a = chunk_args<T>(s, 0, 0, b->d_trial_tot + tot_off);
     a.publish = 0;
+    a.store_dq = 0;
     a.at_ghost = tile_aligned(s->g, tile) ? 1 : 0;
     if (s->cfg.forcing) a.force.table = (T*)(s->ws + s->L.force_table);
     tot_off += (size_t)s->L.ntot * kNQ;

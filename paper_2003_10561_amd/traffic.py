@@ -1,13 +1,18 @@
-"""Algorithmic HBM bytes of one AT RK3 step (what the method must move per grid point).
+"""Algorithmic HBM bytes of one AT step (what the method must move per grid point).
 
 Per point and step the low-storage RK3 reads and writes the state and its register:
 stage 1 reads Q and writes Q and dQ (15 words), stage 2 reads Q and dQ and writes both (20),
 stage 3 reads Q and dQ and writes Q (15) -> 50 words.  Each step publishes the two face layers
 of every PE (u, v, w, T and the 5 face-normal fluxes: 9 words on a fraction
-phi = 4 (1/ex + 1/ey + 1/ez) of the points), and each stage whose face is delayed reads 3 levels
-of those 9 words on the delayed faces' ghost layers: 27 phi p_d per stage, with p_d the fraction
-of (step, face) pairs whose delay is >= 1.  Halo re-reads of neighbouring points are assumed to be
-served by on-chip caches and are not algorithmic.
+phi = 4 (1/ex + 1/ey + 1/ez) of the points).  A step whose faces are delayed reads 3 levels of those
+9 words behind its delayed faces: the levels are the same for the three stages (only the
+extrapolation weights differ, Sec. 2.1), so the method needs them once per step: 27 phi p_d words,
+with p_d the fraction of (step, face) pairs whose delay is >= 1.  Halo re-reads of neighbouring
+points are assumed to be served by on-chip caches and are not algorithmic.
+
+`words_per_point_step_stage_reads` is the looser count that charges the delayed-level reads to
+each of the three stages (81 phi p_d); it is reported beside the minimal one, never used for the
+roofline fraction.
 """
 from __future__ import annotations
 
@@ -17,6 +22,13 @@ def ghost_fraction(n, p) -> float:
 
 
 def words_per_point_step(n, p, p_delayed: float) -> float:
+    """Minimal words per point-step of an RK3 step (delayed levels read once per step)."""
+    phi = ghost_fraction(n, p)
+    return 50.0 + 9.0 * phi + 27.0 * phi * p_delayed
+
+
+def words_per_point_step_stage_reads(n, p, p_delayed: float) -> float:
+    """The same with the delayed levels read again by each of the three stages."""
     phi = ghost_fraction(n, p)
     return 50.0 + 9.0 * phi + 3.0 * 27.0 * phi * p_delayed
 

@@ -215,6 +215,40 @@ def test_autotune_keeps_state_and_uses_cache(tmp_path):
     assert cache.read_text().count("\n") == 1
 
 
+def test_autotune_keeps_adams_bashforth_register():
+    """Adams-Bashforth steps keep dt f^{n-1} in the RK register (Sec. 2.2, Eq. time_ab).  Autotuning
+    a batch that holds such a run (trial stages between steps) must leave that register alone, so
+    that the run's next Adams-Bashforth step is still second order: FP64 fields and statistics of
+    ab2 x3 -> add to a batch -> autotune -> remove -> ab2 x3 match the oracle's six AB2 steps."""
+    say("case ab2 register kept by the autotuner")
+    n, p = (32, 32, 32), (2, 2, 2)
+    q = smooth_state(n, 31)
+    dt, mu = 0.5 * W.default_dt(q), W.default_mu(32)
+    s = atns.Sim(atns.Config(n=n, p=p, dt=dt, mu_ref=mu, max_delay=3, precision="fp64"))
+    s.init_field(q)
+    s.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=10)
+    o = Oracle(OracleConfig(n=n, p=p, dt=dt, mu_ref=mu, max_delay=3))
+    o.init_field(q)
+    o.set_schedule(atns.CAA, L=3, c_r=4, n_steps=10)
+    s.ab2_step(3)
+    b = atns.Batch("fp64")
+    b.add(s)
+    b.autotune(None, reps=1)
+    b.remove(s)
+    b.close()
+    s.ab2_step(3)
+    o.ab2_step(6)
+    ref = o.field()
+    got = s.get_field()
+    errs = [float(np.linalg.norm(got[c] - ref[c]) / np.linalg.norm(ref[c])) for c in range(5)]
+    say("  rel-L2 per component: " + " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) <= 1e-12, errs
+    gs, os_ = s.stats(), o.stats()
+    for k in ("mass_rk", "energy_rk", "K", "eps", "enstrophy"):
+        assert abs(gs[k] - os_[k]) <= 1e-12 * abs(os_[k]), k
+    s.close()
+
+
 def test_fp64_batch_matches_oracle():
     """The parity chain's last link for batches: an FP64 batch against the CPU oracle."""
     say("case fp64 batch vs oracle")
