@@ -1,18 +1,24 @@
-"""Build the gfx950 shared library libatns.so in-tree with hipcc (no JIT, no torch extension)."""
+"""Build the gfx950 shared library libatns.so in-tree with hipcc (no JIT, no torch extension).
+
+Each csrc/*.hip is compiled to an object of its own (in parallel, under _build/ at the repository
+root), then the objects are linked into paper_2003_10561_amd/libatns.so.
+"""
 from __future__ import annotations
 
 import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libatns.so")
+OBJ = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     # packed FP32 instructions stay off for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
@@ -23,12 +29,29 @@ def sources():
     return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
 
 
+def _jobs() -> int:
+    return max(1, min(16, os.cpu_count() or 1, int(os.environ.get("MAX_JOBS", "16"))))
+
+
 def build(verbose: bool = False) -> str:
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           *sources(), "-o", LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
+    objs = []
+    cmds = []
+    for src in sources():
+        obj = os.path.join(OBJ, os.path.splitext(os.path.basename(src))[0] + ".o")
+        objs.append(obj)
+        cmds.append([HIPCC, *FLAGS, *inc, "-c", src, "-o", obj])
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        list(ex.map(run, cmds))
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
+    run(link)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 
