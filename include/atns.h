@@ -206,6 +206,27 @@ ATNS_API const char* at_kernel_name(int32_t kernel);
  * is a member of a batch leaves it. */
 ATNS_API int at_destroy(at_sim* sim);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the statistics of at_stats for a field the caller holds,
+ * with no handle, no allocation (no hipMalloc, hipFree or allocating library routine) and no
+ * synchronisation.
+ *   cfg:       the field's configuration; used: n, precision, gamma, gas_r, prandtl, mu_ref, t_ref,
+ *              mu_exp (the PE grid, delays, forcing and dt play no part), validated as at_create does.
+ *   dev_q:     device conserved state [5][nz][ny][nx] in cfg->precision (read only).
+ *   dev_out:   device memory for one at_stats_t (8-byte aligned), written on the stream: mass, mom,
+ *              energy, K, eps, enstrophy, Mt, umax and nonfinite as at_stats gives them for this
+ *              field (same kernels, same reduction order); step and time are 0 and the _rk fields
+ *              repeat the direct sums (there is no step count or RK history without a handle).
+ *   hip_stream: the stream (NULL = default) on the current device; the call only enqueues.
+ * The per-block partials and the reduction live in a static device array of the library, one per
+ * device, sized for AT_STATS_NOALLOC_MAX_BLOCKS blocks of 64 x 4 points of one z plane
+ * (ceil(nx / 64) ceil(ny / 4) nz <= 65536, e.g. up to 256^3; about 6.9 MB), held until the process
+ * ends.  Every call on a device shares that array and leaves its contents there: calls that overlap
+ * on one device (other streams or host threads without ordering between them) race.
+ * Errors: AT_E_INVAL (NULL pointers, bad config, a grid beyond the block limit), AT_E_HIP. */
+#define AT_STATS_NOALLOC_MAX_BLOCKS 65536
+ATNS_API int at_field_stats_noalloc(const at_config* cfg, const void* dev_q, at_stats_t* dev_out, void* hip_stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Batched runs.  Many independent runs (any grid, PE grid, delays, forcing, time step and
  * viscosity; one precision) advanced together: one launch per kernel per RK stage covers the

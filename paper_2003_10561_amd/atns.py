@@ -27,7 +27,7 @@ EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "a
             "at_batch_create", "at_batch_add", "at_batch_remove", "at_batch_size", "at_batch_step",
             "at_batch_set_tuning", "at_batch_get_tuning", "at_batch_set_stage_tuning",
             "at_batch_get_stage_tuning", "at_batch_autotune", "at_batch_set_graph",
-            "at_batch_graph_stats", "at_batch_destroy", "at_serve"]
+            "at_batch_graph_stats", "at_batch_destroy", "at_serve", "at_field_stats_noalloc"]
 N_TILES = 7
 N_KERNELS = 6
 
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH):
     lib.at_batch_graph_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.at_batch_destroy.argtypes = [vp]
     lib.at_serve.argtypes = [C.POINTER(_ServeConfig), C.POINTER(_Request), i32, vp, C.POINTER(_Result), dp]
+    lib.at_field_stats_noalloc.argtypes = [C.POINTER(_Config), vp, vp, vp]
     _lib = lib
     return lib
 
@@ -403,3 +404,23 @@ def serve(requests, precision: str = "fp32", max_active: int = 64, hbm_budget_by
     out = [{"admit_s": res[i].admit_s, "done_s": res[i].done_s, "status": res[i].status,
             "stats": _stats_dict(res[i].stats)} for i in range(n)]
     return out, float(mk.value)
+
+
+STATS_RECORD_BYTES = C.sizeof(_Stats)
+
+
+def field_stats_noalloc(cfg: Config, dev_q: int, dev_out: int, stream=None):
+    """at_field_stats_noalloc: statistics of the device field at `dev_q` into the device record at
+    `dev_out` (STATS_RECORD_BYTES bytes), enqueued on `stream` (default: torch's current stream)."""
+    import torch
+    lib = load_library()
+    c = cfg.to_c()
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check("at_field_stats_noalloc", lib.at_field_stats_noalloc(C.byref(c), C.c_void_p(dev_q),
+                                                                 C.c_void_p(dev_out), C.c_void_p(st)))
+
+
+def stats_record(raw: bytes) -> dict:
+    """A statistics record (as written by field_stats_noalloc) as a dict."""
+    s = _Stats.from_buffer_copy(raw)
+    return _stats_dict(s)

@@ -29,12 +29,6 @@ int check_step_tables(at_sim* s, int64_t first, int64_t count) {
   return AT_OK;
 }
 
-}  // namespace atns
-
-namespace {
-
-
-
 int validate(const at_config* c) {
   if (!c) return fail(AT_E_INVAL, "config is NULL");
   for (int d = 0; d < 3; ++d) {
@@ -81,6 +75,11 @@ Geom make_geom(const at_config* c) {
   g.ntiles = c->p[0] * c->p[1] * c->p[2];
   return g;
 }
+
+}  // namespace atns
+
+namespace {
+
 
 Layout make_layout(const at_config* c, const Geom& g) {
   const size_t w = c->precision == AT_FP32 ? 4 : 8;

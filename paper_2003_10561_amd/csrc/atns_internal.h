@@ -154,6 +154,10 @@ template <typename T>
 hipError_t launch_force_table(const Geom& g, const double* fhat_step, const int* wv_kx,
                               const int* wv_pair, int npair, T* table, const T* phase_x,
                               hipStream_t stream, LaunchHook* hook);
+// The statistics record of reduced sums `raw` (the output region of launch_stats) into a device
+// at_stats_t, with step 0, time 0 and the RK totals equal to the direct sums.
+hipError_t launch_stats_record(const double* raw, at_stats_t* dst, double npts, double vol, double gamma,
+                               double gas_r, hipStream_t stream);
 int64_t update_blocks(const Geom& g);
 int64_t stats_blocks(const Geom& g);
 

@@ -186,6 +186,29 @@ __global__ __launch_bounds__(256) void k_stats_final(const double* __restrict__ 
   }
 }
 
+// The statistics record of a field from the reduced sums (the conversions at_stats makes on the
+// host), for a caller without a handle: no step count and no RK history, so step and time are 0
+// and the RK-accumulated totals repeat the direct sums.
+__global__ void k_stats_record(const double* __restrict__ st, at_stats_t* __restrict__ o, double npts, double vol,
+                               double gamma, double gas_r) {
+  if (threadIdx.x != 0) return;
+  o->step = 0;
+  o->time = 0.0;
+  o->mass = st[0] * vol;
+  for (int a = 0; a < 3; ++a) o->mom[a] = st[1 + a] * vol;
+  o->energy = st[4] * vol;
+  o->mass_rk = o->mass;
+  for (int a = 0; a < 3; ++a) o->mom_rk[a] = o->mom[a];
+  o->energy_rk = o->energy;
+  o->K = st[5] / npts;
+  o->eps = st[6] / npts;
+  o->enstrophy = st[7] / npts;
+  o->Mt = sqrt(st[8] / npts) / sqrt(gamma * gas_r * (st[9] / npts));
+  o->umax = st[10];
+  o->nonfinite = st[11] != 0.0 ? 1 : 0;
+  o->reserved = 0;
+}
+
 template <typename T>
 __global__ void k_convert(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -274,6 +297,12 @@ hipError_t launch_stats(const Geom& g, const Coef<T>& cf, const T* q, double* pa
   hipLaunchKernelGGL(k_stats_reduce, dim3(kStatRed), dim3(256), 0, stream, part, stats_blocks(g), tot_part,
                      ntot_blocks, mid);
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, stream, (const double*)mid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_record(const double* raw, at_stats_t* dst, double npts, double vol, double gamma,
+                               double gas_r, hipStream_t stream) {
+  hipLaunchKernelGGL(k_stats_record, dim3(1), dim3(64), 0, stream, raw, dst, npts, vol, gamma, gas_r);
   return hipGetLastError();
 }
 

@@ -76,22 +76,32 @@ namespace atns {
 // Schedule and forcing tables must cover steps [first, first + count).
 int check_step_tables(at_sim* s, int64_t first, int64_t count);
 
+// Configuration checks of at_create (AT_OK or the error, with its message recorded).
+int validate(const at_config* c);
+// Grid, PE and ring geometry of a valid configuration.
+Geom make_geom(const at_config* c);
+
 // Removes a run from its batch (called when the run is destroyed).
 void batch_forget(at_batch* b, at_sim* s);
 
 template <typename T>
-Coef<T> make_coef(const at_sim* s) {
+Coef<T> coef_of(const at_config& c) {
   Coef<T> cf{};
-  for (int d = 0; d < 3; ++d) cf.inv12h[d] = (T)(1.0 / (12.0 * (kTwoPi / s->cfg.n[d])));
-  const double cv = s->cfg.gas_r / (s->cfg.gamma - 1.0);
-  const double cp = s->cfg.gamma * s->cfg.gas_r / (s->cfg.gamma - 1.0);
-  cf.gas_r = (T)s->cfg.gas_r;
+  for (int d = 0; d < 3; ++d) cf.inv12h[d] = (T)(1.0 / (12.0 * (kTwoPi / c.n[d])));
+  const double cv = c.gas_r / (c.gamma - 1.0);
+  const double cp = c.gamma * c.gas_r / (c.gamma - 1.0);
+  cf.gas_r = (T)c.gas_r;
   cf.inv_cv = (T)(1.0 / cv);
-  cf.cp_over_pr = (T)(cp / s->cfg.prandtl);
-  cf.mu_ref = (T)s->cfg.mu_ref;
-  cf.inv_tref = (T)(1.0 / s->cfg.t_ref);
-  cf.mu_exp = (T)s->cfg.mu_exp;
+  cf.cp_over_pr = (T)(cp / c.prandtl);
+  cf.mu_ref = (T)c.mu_ref;
+  cf.inv_tref = (T)(1.0 / c.t_ref);
+  cf.mu_exp = (T)c.mu_exp;
   return cf;
+}
+
+template <typename T>
+Coef<T> make_coef(const at_sim* s) {
+  return coef_of<T>(s->cfg);
 }
 
 // Stage arguments of run s at its current state (q = current buffer, q_out = the other).

@@ -1,0 +1,68 @@
+"""The allocation-free statistics entry point (at_field_stats_noalloc) against at_stats.
+
+Two calls in a row through the C ABI on one device - a 64^3 field, then a smaller 32^3 one - each
+compared with at_stats of a handle holding the same field: the statistics that both give (sums of
+the conserved variables, K, <eps>, enstrophy, M_t, max |u|, the non-finite flag) agree to the FP64
+bar (relative 1e-12; they come from the same kernels in the same reduction order).  FP64 and FP32
+fields, and a grid beyond the scratch limit rejected with AT_E_INVAL."""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2003_10561_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2003_10561_amd import atns  # noqa: E402
+
+KEYS = ["mass", "momx", "momy", "momz", "energy", "K", "eps", "enstrophy", "Mt", "umax"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check(n, seed, precision, out):
+    say(f"case noalloc stats {n}^3 {precision}")
+    q = W.make_field(n, seed, 0.3)
+    cfg = atns.Config(n=(n,) * 3, p=(2, 2, 2), dt=W.default_dt(q), mu_ref=W.default_mu(n), max_delay=1,
+                      precision=precision)
+    s = atns.Sim(cfg)
+    s.init_field(q)
+    ref = s.stats()
+    out.zero_()
+    atns.field_stats_noalloc(cfg, s.field_device_ptr(), out.data_ptr())
+    torch.cuda.synchronize()
+    got = atns.stats_record(bytes(out.cpu().numpy().tobytes()))
+    for k in KEYS:
+        err = abs(got[k] - ref[k]) / max(abs(ref[k]), 1e-300)
+        assert err <= 1e-12, (k, got[k], ref[k])
+    for k, kr in (("mass_rk", "mass"), ("momx_rk", "momx"), ("energy_rk", "energy")):
+        assert got[k] == got[kr]
+    assert got["nonfinite"] == 0 and got["step"] == 0
+    s.close()
+    return got
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_noalloc_stats_match_at_stats_two_calls(precision):
+    out = torch.zeros(atns.STATS_RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    a = check(64, 11, precision, out)
+    b = check(32, 12, precision, out)  # second call, smaller grid: the shared scratch is reused
+    assert a["K"] != b["K"]
+
+
+def test_noalloc_rejects_grid_beyond_scratch():
+    cfg = atns.Config(n=(320, 320, 320), p=(1, 1, 1), dt=1e-3, mu_ref=1e-3, max_delay=0)
+    out = torch.zeros(atns.STATS_RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    q = torch.zeros(8, dtype=torch.float64, device="cuda")  # never read: the call is rejected first
+    with pytest.raises(atns.AtError) as e:
+        atns.field_stats_noalloc(cfg, q.data_ptr(), out.data_ptr())
+    assert e.value.rc == atns.AT_E_INVAL
