@@ -16,7 +16,10 @@
 #define NQ 5          /* conserved: rho, rho u, rho v, rho w, E                        */
 #define NPUB 4        /* published primitives per ghost point: u, v, w, T              */
 #define NG 12         /* G_ij = d u_i / d x_j at 3 i + j (9), then d T / d x_j (3)      */
-#define NLAYER 2      /* M = 2: a 4th-order central stencil reaches two points per side */
+/* M, the points a central stencil reaches on each side (2 for the 4th-order, 3 for the 6th-order
+ * scheme), is also the number of boundary layers each PE publishes per face (Sec. 3, Eq. NB), and
+ * t_l = M + 1 the number of past levels an AT extrapolation combines (Appendix B). */
+#define MAXLAYER 3
 #define NFORCE 40
 
 static const double TWO_PI = 6.283185307179586476925286766559;
@@ -29,11 +32,13 @@ static const double RK_C[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
 
 struct ora_sim {
   ora_config c;
+  int M;                 /* layers per face: order / 2 */
+  int tl;                /* levels per AT extrapolation: M + 1 */
   int e[3];              /* tile edge per direction */
   int64_t npts;
   double h[3];
   double cv, cp;
-  int R;                 /* ring levels kept = max_delay + 3 (L + t_l levels, Sec. 3.1) */
+  int R;                 /* ring levels kept = max_delay + t_l (L + t_l levels, Sec. 3.1) */
   double* q;             /* [5][N] */
   double* dq;            /* [5][N] */
   double* prim;          /* [5][N]: rho, u, v, w, T */
@@ -71,11 +76,14 @@ static int tile_index(const ora_sim* s, const int p[3]) {
 
 static int ntiles(const ora_config* c) { return c->p[0] * c->p[1] * c->p[2]; }
 
+static int layers_of(const ora_config* c) { return c->order == 6 ? 3 : 2; }
+
 static int check_config(const ora_config* c) {
+  if (c->order != 4 && c->order != 6) return ORA_E_INVAL;
   for (int d = 0; d < 3; d++) {
     if (c->n[d] <= 0 || c->p[d] <= 0) return ORA_E_INVAL;
     if (c->n[d] % c->p[d] != 0) return ORA_E_INVAL;
-    if (c->n[d] / c->p[d] < 2 * NLAYER) return ORA_E_INVAL;
+    if (c->n[d] / c->p[d] < 2 * layers_of(c)) return ORA_E_INVAL;
   }
   if (c->max_delay < 0 || c->max_delay > 16) return ORA_E_INVAL;
   if (!(c->gamma > 1.0) || !(c->gas_r > 0.0) || !(c->prandtl > 0.0) || !(c->t_ref > 0.0))
@@ -101,6 +109,21 @@ double ora_at_weight(int32_t l, double kappa) {
   return 0.0;
 }
 
+/* Cubic extrapolation from levels n-k .. n-k-3 to t_n + c dt, kappa = k + c: at c = 0 the
+ * Appendix B polynomials of the (1,6) and (2,6) schemes, (k^3+6k^2+11k+6)/6, -(k^3+5k^2+6k)/2,
+ * (k^3+4k^2+3k)/2, -(k^3+3k^2+2k)/6, written here in their factored form. */
+double ora_at_weight6(int32_t l, double kappa) {
+  if (l == 0) return (kappa + 1.0) * (kappa + 2.0) * (kappa + 3.0) / 6.0;
+  if (l == 1) return -kappa * (kappa + 2.0) * (kappa + 3.0) / 2.0;
+  if (l == 2) return kappa * (kappa + 1.0) * (kappa + 3.0) / 2.0;
+  if (l == 3) return -kappa * (kappa + 1.0) * (kappa + 2.0) / 6.0;
+  return 0.0;
+}
+
+static double at_weight(const ora_sim* s, int l, double kappa) {
+  return s->tl == 4 ? ora_at_weight6(l, kappa) : ora_at_weight(l, kappa);
+}
+
 /* ------------------------------------------------------------------ schedule
  * SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output number `counter + 1` of the generator
  * seeded with `seed`. */
@@ -120,9 +143,10 @@ static int saa_draw(uint64_t seed, int64_t n, int t, int f, int nt, int L) {
 }
 
 /* Delay schedules (Sec. 3.1).  CAA (Alg. CAA): PEs exchange every c_r steps, so the delay
- * cycles 0, 1, ..., c_r - 1 with L = c_r - 1; the first c_r steps run synchronously.
- * SAA (Alg. SAA): one exchange per step, delays random and bounded by L; the first L + 3
- * steps (L + t_l, t_l = 3 levels for the 4th-order scheme) run synchronously. */
+ * cycles 0, 1, ..., c_r - 1 with L = c_r - 1; the first max(c_r, t_l) steps run synchronously
+ * (enough levels for one extrapolation exist from step t_l - 1 on).
+ * SAA (Alg. SAA): one exchange per step, delays random and bounded by L; the first L + t_l
+ * steps (t_l = 3 levels for the 4th-order scheme, 4 for the 6th-order one) run synchronously. */
 int ora_set_schedule(ora_sim* s, int32_t mode, int32_t L, int32_t c_r, uint64_t seed,
                      const int8_t* table, int64_t n_steps) {
   if (!s || n_steps < 0) return ORA_E_INVAL;
@@ -133,8 +157,9 @@ int ora_set_schedule(ora_sim* s, int32_t mode, int32_t L, int32_t c_r, uint64_t 
     /* all zero */
   } else if (mode == ORA_CAA) {
     if (c_r < 1 || L != c_r - 1) { free(t); return ORA_E_INVAL; }
+    const int warm = c_r > s->tl ? c_r : s->tl;
     for (int64_t n = 0; n < n_steps; n++) {
-      int k = (n < c_r) ? 0 : (int)(n % c_r);
+      int k = (n < warm) ? 0 : (int)(n % c_r);
       for (int i = 0; i < nt * 6; i++) t[n * nt * 6 + i] = (int8_t)k;
     }
   } else if (mode == ORA_SAA) {
@@ -142,7 +167,7 @@ int ora_set_schedule(ora_sim* s, int32_t mode, int32_t L, int32_t c_r, uint64_t 
     for (int64_t n = 0; n < n_steps; n++)
       for (int ti = 0; ti < nt; ti++)
         for (int f = 0; f < 6; f++)
-          t[(n * nt + ti) * 6 + f] = (int8_t)((n < L + 3) ? 0 : saa_draw(seed, n, ti, f, nt, L));
+          t[(n * nt + ti) * 6 + f] = (int8_t)((n < L + s->tl) ? 0 : saa_draw(seed, n, ti, f, nt, L));
   } else if (mode == ORA_EXPLICIT) {
     if (!table) { free(t); return ORA_E_INVAL; }
     memcpy(t, table, (size_t)n_steps * nt * 6);
@@ -150,11 +175,11 @@ int ora_set_schedule(ora_sim* s, int32_t mode, int32_t L, int32_t c_r, uint64_t 
     free(t);
     return ORA_E_INVAL;
   }
-  /* every delayed read needs levels n-k .. n-k-2 >= 0 and still in the ring */
+  /* every delayed read needs levels n-k .. n-k-(t_l-1) >= 0 and still in the ring */
   for (int64_t n = 0; n < n_steps; n++)
     for (int i = 0; i < nt * 6; i++) {
       int k = t[n * nt * 6 + i];
-      if (k < 0 || k > s->c.max_delay || (k > 0 && n - k - 2 < 0)) { free(t); return ORA_E_SCHEDULE; }
+      if (k < 0 || k > s->c.max_delay || (k > 0 && n - k - (s->tl - 1) < 0)) { free(t); return ORA_E_SCHEDULE; }
     }
   free(s->sched);
   s->sched = t;
@@ -173,17 +198,18 @@ static int delay_of(const ora_sim* s, int tile, int face) {
 }
 
 /* ------------------------------------------------------------------ ring of published data
- * Each PE publishes, on each of its faces, the two own layers next to that face (the
- * boundary points N_B of Sec. 3 with M = 2).  Layer j in {0,1,2,3} of tile t along d holds
- * local index {0, 1, e-2, e-1}. */
+ * Each PE publishes, on each of its faces, the M own layers next to that face (the boundary
+ * points N_B of Sec. 3).  Layer j in {0 .. 2M-1} of tile t along d holds local index
+ * {0 .. M-1, e-M .. e-1}. */
 static int64_t slab_index(const ora_sim* s, int d, const int r[3]) {
   const int e = s->e[d];
   const int l = r[d] % e;
+  const int M = s->M;
   int j;
-  if (l < NLAYER) j = l;
-  else if (l >= e - NLAYER) j = l - e + 2 * NLAYER;
+  if (l < M) j = l;
+  else if (l >= e - M) j = l - e + 2 * M;
   else return -1;
-  const int plane = (r[d] / e) * 2 * NLAYER + j;
+  const int plane = (r[d] / e) * 2 * M + j;
   const int a = (d == 0) ? 1 : 0;          /* faster transverse direction */
   const int b = (d == 2) ? 1 : 2;          /* slower transverse direction */
   return ((int64_t)plane * s->c.n[b] + r[b]) * s->c.n[a] + r[a];
@@ -215,32 +241,42 @@ static double seen(ora_sim* s, int kind, int comp, const double* cur, int d, con
   if (k == 0) return cur[ir];
   const double kap = (double)k + RK_C[stage];
   double v = 0.0;
-  for (int l = 0; l < 3; l++)
-    v += ora_at_weight(l, kap) * ring_read(s, kind, d, comp, s->step - k - l, r);
+  for (int l = 0; l < s->tl; l++)
+    v += at_weight(s, l, kap) * ring_read(s, kind, d, comp, s->step - k - l, r);
   return v;
 }
 
-/* 4th-order central first derivative, the k = 0 row of the (1,4) schemes of Appendix B:
- * (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / (12 h); with AT ghost values substituted. */
+/* Central first derivatives, the k = 0 rows of the Appendix B schemes:
+ * (1,4): (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / (12 h);
+ * (1,6): (-f_{i-3} + 9 f_{i-2} - 45 f_{i-1} + 45 f_{i+1} - 9 f_{i+2} + f_{i+3}) / (60 h);
+ * v[] holds f at offsets -M .. -1, +1 .. +M. */
+static double d1_central(int order, const double* v, double h) {
+  if (order == 6) return (-v[0] + 9.0 * v[1] - 45.0 * v[2] + 45.0 * v[3] - 9.0 * v[4] + v[5]) / (60.0 * h);
+  return (v[0] - 8.0 * v[1] + 8.0 * v[2] - v[3]) / (12.0 * h);
+}
+
+/* The central derivative with AT ghost values substituted. */
 static double d1_at(ora_sim* s, int kind, int comp, const double* cur, int d, const int p[3],
                     int stage) {
-  const double fm2 = seen(s, kind, comp, cur, d, p, -2, stage);
-  const double fm1 = seen(s, kind, comp, cur, d, p, -1, stage);
-  const double fp1 = seen(s, kind, comp, cur, d, p, 1, stage);
-  const double fp2 = seen(s, kind, comp, cur, d, p, 2, stage);
-  return (fm2 - 8.0 * fm1 + 8.0 * fp1 - fp2) / (12.0 * s->h[d]);
+  double v[2 * MAXLAYER];
+  int i = 0;
+  for (int m = -s->M; m <= s->M; m++)
+    if (m != 0) v[i++] = seen(s, kind, comp, cur, d, p, m, stage);
+  return d1_central(s->c.order, v, s->h[d]);
 }
 
 /* The same stencil on the periodic grid with every point current (standard FD, Eq. du). */
 static double d1_periodic(const ora_config* c, const double* f, int d, const int p[3], double h) {
-  double v[4];
-  const int ms[4] = {-2, -1, 1, 2};
-  for (int i = 0; i < 4; i++) {
+  double v[2 * MAXLAYER];
+  const int M = layers_of(c);
+  int i = 0;
+  for (int m = -M; m <= M; m++) {
+    if (m == 0) continue;
     int r[3] = {p[0], p[1], p[2]};
-    r[d] = wrap(p[d] + ms[i], c->n[d]);
-    v[i] = f[idx3(c, r[0], r[1], r[2])];
+    r[d] = wrap(p[d] + m, c->n[d]);
+    v[i++] = f[idx3(c, r[0], r[1], r[2])];
   }
-  return (v[0] - 8.0 * v[1] + 8.0 * v[2] - v[3]) / (12.0 * h);
+  return d1_central(c->order, v, h);
 }
 
 /* ------------------------------------------------------------------ physics (Sec. 2)
@@ -339,6 +375,8 @@ int ora_create(const ora_config* cfg, ora_sim** out) {
   ora_sim* s = (ora_sim*)calloc(1, sizeof(ora_sim));
   if (!s) return ORA_E_NOMEM;
   s->c = *cfg;
+  s->M = layers_of(cfg);
+  s->tl = s->M + 1;
   s->npts = (int64_t)cfg->n[0] * cfg->n[1] * cfg->n[2];
   for (int d = 0; d < 3; d++) {
     s->e[d] = cfg->n[d] / cfg->p[d];
@@ -346,7 +384,7 @@ int ora_create(const ora_config* cfg, ora_sim** out) {
   }
   s->cv = cfg->gas_r / (cfg->gamma - 1.0);
   s->cp = cfg->gamma * cfg->gas_r / (cfg->gamma - 1.0);
-  s->R = cfg->max_delay + 3;
+  s->R = cfg->max_delay + s->tl;
   const int64_t N = s->npts;
   s->q = (double*)calloc((size_t)NQ * N, sizeof(double));
   s->dq = (double*)calloc((size_t)NQ * N, sizeof(double));
@@ -358,7 +396,7 @@ int ora_create(const ora_config* cfg, ora_sim** out) {
   int ok = s->q && s->dq && s->prim && s->grad && s->flux && s->rhs && s->slot_level;
   for (int d = 0; d < 3; d++) {
     const int a = (d == 0) ? 1 : 0, b = (d == 2) ? 1 : 2;
-    s->slab[d] = (int64_t)2 * NLAYER * cfg->p[d] * cfg->n[a] * cfg->n[b];
+    s->slab[d] = (int64_t)2 * s->M * cfg->p[d] * cfg->n[a] * cfg->n[b];
     s->ring_pub[d] = (double*)malloc(sizeof(double) * s->R * NPUB * s->slab[d]);
     s->ring_flux[d] = (double*)malloc(sizeof(double) * s->R * NQ * s->slab[d]);
     ok = ok && s->ring_pub[d] && s->ring_flux[d];
@@ -701,6 +739,7 @@ int64_t ora_count_at_points(const ora_config* cfg) {
   if (check_config(cfg)) return -1;
   int e[3];
   for (int d = 0; d < 3; d++) e[d] = cfg->n[d] / cfg->p[d];
+  const int M = layers_of(cfg);
   int64_t cnt = 0;
   for (int z = 0; z < cfg->n[2]; z++)
     for (int y = 0; y < cfg->n[1]; y++)
@@ -708,7 +747,7 @@ int64_t ora_count_at_points(const ora_config* cfg) {
         const int p[3] = {x, y, z};
         int ghost = 0;
         for (int d = 0; d < 3 && !ghost; d++)
-          for (int m = -NLAYER; m <= NLAYER; m++) {
+          for (int m = -M; m <= M; m++) {
             const int l = p[d] % e[d] + m;
             if (l < 0 || l >= e[d]) ghost = 1;
           }

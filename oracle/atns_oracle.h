@@ -10,7 +10,8 @@
  *   * compressible NS right-hand side in total-energy flux form (Sec. 2, Eqs. cont, mome, ie
  *     recast so that mass, momentum and total energy telescope, Sec. 2.1 Eqs. convf-ts4);
  *   * 4th-order central first derivatives, with AT ghost values at every face of every
- *     virtual processing element (Sec. 2.1 Eq. at; Appendix B Table atschemes, (1,4) rows);
+ *     virtual processing element (Sec. 2.1 Eq. at; Appendix B Table atschemes, (1,4) rows), or
+ *     6th-order ones with the (1,6) rows (Sec. 4.1.2; Appendix B);
  *   * delays per (step, PE, face) from the periodic (CAA, Sec. 3.1.2 Alg. CAA) or random
  *     (SAA, Sec. 3.1.1 Alg. SAA) rules, or from an explicit table;
  *   * low-storage third-order Runge-Kutta (Williamson's 2N scheme) with a fixed time step
@@ -34,8 +35,10 @@ enum { ORA_SYNC = 0, ORA_CAA = 1, ORA_SAA = 2, ORA_EXPLICIT = 3 };
 typedef struct {
   int32_t n[3];          /* grid points per direction (x, y, z) on [0, 2 pi)^3            */
   int32_t p[3];          /* virtual PEs per direction; n[d] % p[d] == 0, n[d]/p[d] >= 4    */
-  int32_t max_delay;     /* largest delay any face may use; ring keeps max_delay + 3 levels */
+  int32_t max_delay;     /* largest delay any face may use; ring keeps max_delay + t_l levels */
   int32_t forcing;       /* 0 / 1                                                          */
+  int32_t order;         /* spatial order: 4 ((1,4) AT rows, t_l = 3 levels, M = 2 layers) or */
+                         /* 6 ((1,6) AT rows, t_l = 4 levels, M = 3 layers)                   */
   double gamma, prandtl, gas_r, mu_ref, t_ref, mu_exp, dt;
 } ora_config;
 
@@ -67,7 +70,8 @@ int64_t ora_step(const ora_sim* s);
 
 /* test hooks */
 int ora_rhs_periodic_standard(const ora_config* cfg, const double* q, double* out);
-double ora_at_weight(int32_t l, double kappa);
+double ora_at_weight(int32_t l, double kappa);          /* (1,4): quadratic, l = 0..2 */
+double ora_at_weight6(int32_t l, double kappa);         /* (1,6): cubic, l = 0..3     */
 int64_t ora_count_at_points(const ora_config* cfg);
 int ora_forcing_field(const ora_config* cfg, const double* fhat_step, double* out /*[3][N]*/);
 uint64_t ora_splitmix64(uint64_t seed, uint64_t counter);

@@ -32,7 +32,7 @@ def build() -> str:
 
 class _Cfg(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("p", C.c_int32 * 3), ("max_delay", C.c_int32),
-                ("forcing", C.c_int32), ("gamma", C.c_double), ("prandtl", C.c_double),
+                ("forcing", C.c_int32), ("order", C.c_int32), ("gamma", C.c_double), ("prandtl", C.c_double),
                 ("gas_r", C.c_double), ("mu_ref", C.c_double), ("t_ref", C.c_double),
                 ("mu_exp", C.c_double), ("dt", C.c_double)]
 
@@ -50,6 +50,7 @@ class OracleConfig:
     gas_r: float = 1.0
     t_ref: float = 1.0
     mu_exp: float = 0.76
+    order: int = 4
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -60,6 +61,7 @@ class OracleConfig:
             c.p[d] = int(p[d])
         c.max_delay = int(self.max_delay)
         c.forcing = int(bool(self.forcing))
+        c.order = int(self.order)
         for k in ("gamma", "prandtl", "gas_r", "mu_ref", "t_ref", "mu_exp", "dt"):
             setattr(c, k, float(getattr(self, k)))
         return c
@@ -103,6 +105,8 @@ def _load():
         lib.ora_rhs_periodic_standard.argtypes = [C.POINTER(_Cfg), dp, dp]
         lib.ora_at_weight.argtypes = [i32, C.c_double]
         lib.ora_at_weight.restype = C.c_double
+        lib.ora_at_weight6.argtypes = [i32, C.c_double]
+        lib.ora_at_weight6.restype = C.c_double
         lib.ora_count_at_points.argtypes = [C.POINTER(_Cfg)]
         lib.ora_count_at_points.restype = i64
         lib.ora_forcing_field.argtypes = [C.POINTER(_Cfg), dp, dp]
@@ -223,6 +227,10 @@ class Oracle:
     @staticmethod
     def at_weight(l, kappa) -> float:
         return float(_load().ora_at_weight(int(l), float(kappa)))
+
+    @staticmethod
+    def at_weight6(l, kappa) -> float:
+        return float(_load().ora_at_weight6(int(l), float(kappa)))
 
     @staticmethod
     def count_at_points(cfg: OracleConfig) -> int:

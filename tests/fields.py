@@ -101,6 +101,7 @@ def read_appb(path):
             continue
         head, stencil, side, div = [s.strip() for s in line.split("|")]
         hs = head.split()
-        rows.append(dict(side=hs[0], l=int(hs[1]), w=(float(hs[2]), float(hs[3]), float(hs[4])),
+        # w: the coefficients of the weight polynomial in k, highest power first
+        rows.append(dict(side=hs[0], l=int(hs[1]), w=tuple(float(v) for v in hs[2:]),
                          a=[float(v) for v in stencil.split()], delayed=side, div=float(div)))
     return rows

@@ -1,10 +1,12 @@
 """Served runs through the C ABI (at_serve): continuous batching returns, for every request, the
-state and statistics of the same run stepped alone; admission respects the limits."""
+state and statistics of the same run stepped alone and, in FP64, those of the CPU oracle run on
+the same inputs; admission respects the limits."""
 import sys
 
 import numpy as np
 import pytest
 
+from oracle import Oracle, OracleConfig
 from paper_2003_10561_amd import workload as W
 
 pytestmark = pytest.mark.gpu
@@ -70,6 +72,37 @@ def test_served_equals_alone():
         for k in ("mass_rk", "energy_rk", "K", "eps", "enstrophy", "step"):
             assert o["stats"][k] == st[k], (j, k)
         assert o["stats"]["step"] == r["steps"]
+
+
+def test_served_fp64_matches_oracle():
+    """Eight FP64 requests (16^3 - 32^3, synchronous, periodic and random delays) through three slots,
+    so that runs join and leave while others are on the GPU: each final state matches the CPU FP64
+    oracle run of that request within relative L2 1e-12 per component, and its statistics (including
+    the RK-accumulated totals) within 1e-12."""
+    say("case serve fp64 8 requests, 3 slots, vs oracle")
+    reqs = trace(17, 8, 0.2)
+    res, makespan = atns.serve(reqs, precision="fp64", max_active=3, tile=5, zchunk=16)
+    say(f"  makespan {makespan:.3f} s")
+    for j, (r, o) in enumerate(zip(reqs, res)):
+        assert o["status"] == 0, (j, o["status"])
+        n, p, L = r["n"], r["p"], r["L"]
+        orc = Oracle(OracleConfig(n=(n,) * 3, p=(p,) * 3, dt=r["dt"], mu_ref=r["mu_ref"], max_delay=L))
+        orc.init_field(r["q0"])
+        if r["mode"] == atns.CAA:
+            orc.set_schedule(atns.CAA, L=L, c_r=L + 1, n_steps=r["steps"] + 1)
+        elif r["mode"] == atns.SAA:
+            orc.set_schedule(atns.SAA, L=L, seed=r["seed"], n_steps=r["steps"] + 1)
+        else:
+            orc.set_schedule(atns.SYNC, n_steps=r["steps"] + 1)
+        orc.rk_step(r["steps"])
+        ref, ost = orc.field(), orc.stats()
+        got = r["q_final"]
+        errs = [float(np.linalg.norm(got[c] - ref[c]) / np.linalg.norm(ref[c])) for c in range(5)]
+        say(f"  request {j}: n={n} mode={r['mode']} L={L} steps={r['steps']} rel-L2 max {max(errs):.2e}")
+        assert max(errs) <= 1e-12, (j, errs)
+        for k in ("mass", "energy", "mass_rk", "energy_rk", "K", "eps", "enstrophy", "Mt", "umax"):
+            assert abs(o["stats"][k] - ost[k]) <= 1e-12 * abs(ost[k]), (j, k, o["stats"][k], ost[k])
+        assert o["stats"]["step"] == ost["step"] == r["steps"]
 
 
 def test_admission_limits():

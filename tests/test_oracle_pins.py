@@ -719,3 +719,217 @@ def test_forcing_held_fixed_within_step():
     assert 3.6 < ratio < 4.4, errs
     # and the step moved the state by dt * source to leading order
     assert errs[1] < 1e-3 * 1e-3 * np.abs(src).max(), errs
+
+
+# ------------------------------------------------------------------ sixth-order AT (Sec. 4.1.2; Appendix B, (1,6) rows)
+def cfg6(n, p, dt=0.01, mu=0.0, L=3, **kw):
+    return cfg_for(n, p, dt=dt, mu=mu, L=L, order=6, **kw)
+
+
+def _poly(w, k):
+    return sum(c * k ** (len(w) - 1 - i) for i, c in enumerate(w))
+
+
+def test_appb6_weights_at_integer_delay_and_stage_times():
+    """w_l(k) of the cubic extrapolation equal the (1,6) Appendix B polynomials at integer k and sum
+    to one; at k = 0 the scheme is the standard one (Sec. 2.1).  At non-integer kappa = k + c_s (RK
+    stage times) they are the weights that extrapolate every cubic in time exactly: the solution of
+    the Vandermonde system on the level times -(kappa + l), solved here with numpy."""
+    rows = F.read_appb(os.path.join(GOLD, "appb_at16.txt"))
+    assert len(rows) == 8 and all(len(r["w"]) == 4 and len(r["a"]) == 7 for r in rows)
+    for k in range(0, 6):
+        for r in rows:
+            assert Oracle.at_weight6(r["l"], float(k)) == pytest.approx(_poly(r["w"], k), rel=1e-15, abs=1e-13)
+        assert sum(Oracle.at_weight6(l, float(k)) for l in range(4)) == pytest.approx(1.0, abs=1e-13)
+    assert [Oracle.at_weight6(l, 0.0) for l in range(4)] == [1.0, 0.0, 0.0, 0.0]
+    assert [Oracle.at_weight6(l, 3.0) for l in range(4)] == [20.0, -45.0, 36.0, -10.0]
+    for kap in (0.25, 1.0 / 3.0, 1.75, 3.75):
+        tau = -(kap + np.arange(4.0))
+        V = np.vander(tau, 4, increasing=True).T  # rows: sum_l w_l tau_l^j = delta_j0
+        w = np.linalg.solve(V, np.array([1.0, 0.0, 0.0, 0.0]))
+        got = [Oracle.at_weight6(l, kap) for l in range(4)]
+        np.testing.assert_allclose(got, w, rtol=1e-12, atol=1e-12)
+
+
+def _appb_line(levels, n, e, kl, kr, h, rows, current_override=None):
+    """The printed AT rows (either order) along one periodic line; as _appb_derivative_1d."""
+    N = levels[n].shape[0]
+    cur = levels[n] if current_override is None else current_override
+    rows = [r for r in rows if r["side"] == "left"]
+    M = (len(rows[0]["a"]) - 1) // 2
+    offs = list(range(-M, M + 1))
+    out = np.zeros(N)
+    for i in range(N):
+        t, loc = divmod(i, e)
+        k = kl[t] if loc < M else (kr[t] if loc >= e - M else 0)
+        acc = 0.0
+        for r in rows:
+            s = 0.0
+            for a, m in zip(r["a"], offs):
+                outside = not (0 <= loc + m < e)
+                j = (i + m) % N
+                s += a * (levels[n - k - r["l"]][j] if (outside and k > 0) else cur[j])
+            acc += _poly(r["w"], k) * s
+        out[i] = acc / (rows[0]["div"] * h)
+    return out
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_appb6_stencil_mass_flux(axis):
+    """Continuity RHS with the sixth-order scheme equals -(1,6) AT derivative of the mass flux as
+    printed in Appendix B (misprints corrected, see the golden file), per-face delays 0..3 and
+    arbitrary history levels: checks each cubic weight, each level index and the 3-point ghosts."""
+    rng = np.random.default_rng(17 + axis)
+    N, e = 24, 6
+    n = [6, 6, 6]
+    n[axis] = N
+    p = [1, 1, 1]
+    p[axis] = N // e
+    nlev = 7
+    cur = nlev - 1
+    U = 0.7
+    lines = [1.0 + 0.2 * rng.standard_normal(N) for _ in range(nlev)]
+    shape = (n[2], n[1], n[0])
+    qs = []
+    for m in range(nlev):
+        ls = [1, 1, 1]
+        ls[2 - axis] = N
+        rho = np.broadcast_to(lines[m].reshape(ls), shape).copy()
+        vel = [np.zeros(shape) for _ in range(3)]
+        vel[axis][:] = U
+        qs.append(F.conservative(rho, vel[0], vel[1], vel[2], 1.0 / rho))
+    cfg = cfg6(n, p, L=3)
+    tab = np.zeros((nlev + 1, cfg.ntiles, 6), dtype=np.int8)
+    tab[cur] = rng.integers(0, 4, size=(cfg.ntiles, 6))  # transverse fluxes vanish at every level
+    tab[cur, :, 2 * axis] = [0, 1, 2, 3]  # every delay on the faces along the axis
+    tab[cur, :, 2 * axis + 1] = [3, 1, 0, 2]
+    o = Oracle(cfg)
+    o.init_field(np.ascontiguousarray(np.stack(qs)), nlev)
+    o.set_schedule(EXPLICIT, table=tab)
+    r = o.rhs()
+    kl = [int(tab[cur, t, 2 * axis]) for t in range(cfg.ntiles)]
+    kr = [int(tab[cur, t, 2 * axis + 1]) for t in range(cfg.ntiles)]
+    rows = F.read_appb(os.path.join(GOLD, "appb_at16.txt"))
+    expect = -_appb_line([U * l for l in lines], cur, e, kl, kr, 2 * math.pi / N, rows)
+    got = np.moveaxis(r[0], 2 - axis, 0).reshape(N, -1)
+    for col in range(got.shape[1]):
+        np.testing.assert_allclose(got[:, col], expect, rtol=0, atol=1e-12)
+    assert 3 in kl + kr
+
+
+@pytest.mark.parametrize("p", [(2, 2, 1), (1, 1, 1), (3, 2, 2)])
+def test_order6_zero_delay_is_standard_bitwise(p):
+    q = W.make_field(24, 3)
+    cfg = cfg6((24, 24, 24), p, mu=0.02)
+    o = Oracle(cfg)
+    o.init_field(q)
+    o.set_schedule(SYNC, n_steps=4)
+    np.testing.assert_array_equal(o.rhs(), Oracle.rhs_periodic_standard(cfg, q))
+
+
+def test_order6_conservation_synchronous():
+    q = W.make_field(24, 4)
+    cfg = cfg6((24, 24, 24), (2, 2, 2), dt=W.default_dt(q), mu=W.default_mu(24))
+    o = Oracle(cfg)
+    o.init_field(q)
+    o.set_schedule(SYNC, n_steps=4)
+    r = o.rhs()
+    for c in range(5):
+        assert abs(r[c].sum()) <= 1e-13 * np.abs(r[c]).sum()
+
+
+def test_order6_modified_wavenumber():
+    """rho = 1 + eps sin(m x), u = U e_x, p uniform, mu = 0: continuity RHS = -U eps k'_m cos(m x)
+    with the 6th-order modified wavenumber k'_m = (45 sin mh - 9 sin 2mh + sin 3mh) / (30 h)."""
+    N = 24
+    h = 2 * math.pi / N
+    X = F.grid((N, N, N))
+    for m in (1, 4):
+        eps, U = 0.1, 0.4
+        rho = 1.0 + eps * np.sin(m * X[0])
+        z = np.zeros_like(rho)
+        o = Oracle(cfg6((N, N, N), (2, 2, 2)))
+        o.init_field(F.conservative(rho, U + z, z, z, 1.0 / rho))
+        o.set_schedule(SYNC, n_steps=1)
+        kp = (45 * math.sin(m * h) - 9 * math.sin(2 * m * h) + math.sin(3 * m * h)) / (30 * h)
+        np.testing.assert_allclose(o.rhs()[0], -U * eps * kp * np.cos(m * X[0]), rtol=0, atol=1e-13)
+
+
+def test_cubic_time_levels_are_extrapolated_exactly():
+    """Fluxes varying cubically in time: the 4-level AT ghost equals the current value, so the AT
+    RHS equals the synchronous one to rounding for every delay; the 4th-order scheme (3 levels) is
+    not exact on the same data."""
+    rng = np.random.default_rng(6)
+    N, nlev = 24, 7
+    a, b, c, d = (rng.standard_normal((N, N, N)) * s for s in (0.2, 0.05, 0.01, 0.003))
+    qs = []
+    for m in range(nlev):
+        rho = 1.0 + a + b * m + c * m * m + d * m ** 3
+        z = np.zeros_like(rho)
+        qs.append(F.conservative(rho, 0.5 + z, z, z, 1.0 / rho))
+    q = np.ascontiguousarray(np.stack(qs))
+    tab = np.zeros((nlev + 1, 8, 6), dtype=np.int8)
+    tab[nlev - 1] = rng.integers(1, 4, size=(8, 6))
+    out = {}
+    for order in (6, 4):
+        cfg = cfg_for((N, N, N), (2, 2, 2), mu=0.0, L=3, order=order)
+        o = Oracle(cfg)
+        nl = nlev if order == 6 else 6
+        o.init_field(np.ascontiguousarray(q[nlev - nl:]), nl)
+        o.set_schedule(EXPLICIT, table=tab[nlev - nl:])
+        out[order] = (o.rhs()[0], Oracle.rhs_periodic_standard(cfg, qs[-1])[0])
+    r, std = out[6]
+    np.testing.assert_allclose(r, std, rtol=0, atol=1e-11 * np.abs(std).max())
+    r4, std4 = out[4]
+    assert np.abs(r4 - std4).max() > 1e-6 * np.abs(std4).max()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [1, 3])
+def test_rhs_sixth_order_under_delays(k):
+    """Full NS RHS with (1,6) AT ghosts at every PE face converges at 6th order to the exact RHS
+    when dt ~ dx^2 (the cubic extrapolation error O(dt^4 / dx) is then O(dx^7))."""
+    errs = []
+    for N in (16, 32, 64):
+        h = 2 * math.pi / N
+        dt = 0.5 * h * h
+        nlev = 7
+        cfg = cfg6((N, N, N), (2, 2, 2), dt=dt, mu=0.05)
+        tab = np.zeros((nlev + 1, 8, 6), dtype=np.int8)
+        tab[nlev - 1] = k
+        o = Oracle(cfg)
+        o.init_field(_analytic_history((N, N, N), nlev, dt), nlev)
+        o.set_schedule(EXPLICIT, table=tab)
+        errs.append(np.abs(o.rhs() - F.analytic_rhs((N, N, N), 0.0)).max())
+    order = math.log2(errs[1] / errs[2])
+    assert order >= 5.5, errs
+
+
+def test_order6_schedules_and_validation():
+    """t_l = 4 levels: SAA runs synchronously for L + 4 steps, CAA for max(c_r, 4); a delay k at
+    step n needs n - k - 3 >= 0; the ring keeps L + 4 levels."""
+    cfg = cfg6((24, 24, 24), (2, 2, 2), L=2)
+    o = Oracle(cfg)
+    o.init_field(W.make_field(24, 1))
+    o.set_schedule(SAA, L=2, seed=102, n_steps=40)
+    t = o.get_schedule(40)
+    assert (t[:6] == 0).all() and (t[6:] > 0).any() and t.max() == 2
+    o.set_schedule(CAA, L=1, c_r=2, n_steps=12)
+    t = o.get_schedule(12)
+    assert (t[:4] == 0).all() and all((t[n] == n % 2).all() for n in range(4, 12))
+    bad = np.zeros((8, 8, 6), dtype=np.int8)
+    bad[4, 0, 0] = 2  # needs level 4 - 2 - 3 = -1
+    with pytest.raises(OracleError):
+        o.set_schedule(EXPLICIT, table=bad)
+    bad[4, 0, 0] = 1  # levels 3 .. 0: fine
+    o.set_schedule(EXPLICIT, table=bad)
+    with pytest.raises(OracleError):
+        o.init_field(np.stack([W.make_field(24, 1)] * 7), 7)  # more levels than L + 4 = 6
+
+
+def test_order6_boundary_point_fraction():
+    """Eq. NB with M = 3 boundary layers: N_B = N_T - (ex - 6)(ey - 6)(ez - 6) per PE."""
+    for ex, ey, ez in ((16, 16, 16), (32, 16, 16), (12, 8, 24)):
+        cfg = cfg6((2 * ex, 2 * ey, 2 * ez), (2, 2, 2))
+        nt = ex * ey * ez
+        assert Oracle.count_at_points(cfg) == 8 * (nt - (ex - 6) * (ey - 6) * (ez - 6))
