@@ -52,10 +52,11 @@ typedef enum at_status {
 
 typedef enum at_precision { AT_FP64 = 0, AT_FP32 = 1 } at_precision;
 
-/* Delay modes (Sec. 3.1).  SYNC: every face reads the current level.  CAA (Alg. CAA): PEs
- * exchange every c_r steps, so from step c_r on the delay is n mod c_r on every face, with
- * L = c_r - 1.  SAA (Alg. SAA): one exchange per step, delays random and bounded by L; from
- * step L + 3 on each (step, PE, face) delay is an independent uniform draw in {0..L} made with
+/* Delay modes (Sec. 3.1).  t_l is the number of levels one AT extrapolation combines: 3 for the
+ * fourth-order scheme, 4 for the sixth-order one.  SYNC: every face reads the current level.
+ * CAA (Alg. CAA): PEs exchange every c_r steps, so from step max(c_r, t_l) on the delay is
+ * n mod c_r on every face, with L = c_r - 1.  SAA (Alg. SAA): one exchange per step, delays random
+ * and bounded by L; from step L + t_l on each (step, PE, face) delay is an independent uniform draw in {0..L} made with
  * SplitMix64 (Steele, Lea & Flood, 2014): z = output number ((n P + t) 6 + f) + 1 of the
  * generator seeded with `seed`, k = ((z >> 32) (L + 1)) >> 32.  EXPLICIT: a caller table. */
 typedef enum at_delay_mode { AT_SYNC = 0, AT_CAA = 1, AT_SAA = 2, AT_EXPLICIT = 3 } at_delay_mode;
@@ -63,8 +64,10 @@ typedef enum at_delay_mode { AT_SYNC = 0, AT_CAA = 1, AT_SAA = 2, AT_EXPLICIT = 
 typedef struct at_config {
   int32_t n[3];        /* grid points in x, y, z; h_d = 2 pi / n[d]                            */
   int32_t p[3];        /* virtual PEs per direction; n[d] % p[d] == 0 and n[d] / p[d] >= 4      */
-  int32_t order;       /* spatial order; 4 is the only value accepted                           */
-  int32_t max_delay;   /* largest delay any face may use (0..8); the ring keeps max_delay + 3   */
+  int32_t order;       /* spatial order: 4 (the (1,4) rows of Appendix B: 2 face layers, t_l = 3)  */
+                       /* or 6 (the (1,6) rows, Sec. 4.1.2: 3 face layers, t_l = 4; PE edges >= 6, */
+                       /* unforced, single runs only)                                            */
+  int32_t max_delay;   /* largest delay any face may use (0..8); the ring keeps max_delay + t_l */
                        /* levels (L + t_l levels per PE, Sec. 3.1)                              */
   int32_t precision;   /* AT_FP64 or AT_FP32 (fields, fluxes, ring and stencils); reductions of */
                        /* statistics and of the conserved totals are FP64 in both modes         */
@@ -102,10 +105,11 @@ ATNS_API const char* at_last_error(void);
 
 /* Bytes of device workspace at_create needs for `cfg` (0 if cfg is invalid).  Holds two conserved
  * state buffers (a stage reads one and writes the other), the RK register, the ring of
- * published face layers: (max_delay + 3) levels x 9 components (u, v, w, T and the face-normal flux of the five
- * conserved variables) x 4 (1/ex + 1/ey + 1/ez) N^3 points, and three level-sized buffers of the
- * AT sums of the face-layer readers (one per RK stage of a step; for the x and y faces, when the
- * delayed-stage tile is aligned with the PEs, the extrapolated values themselves), plus small
+ * published face layers: (max_delay + t_l) levels x 9 components (u, v, w, T and the face-normal flux of the five
+ * conserved variables) x 2 M (1/ex + 1/ey + 1/ez) N^3 points (M = order / 2 layers per face); for
+ * order 4 three level-sized buffers of the AT sums of the face-layer readers (one per RK stage of
+ * a step; for the x and y faces, when the delayed-stage tile is aligned with the PEs, the
+ * extrapolated values themselves), for order 6 the 15 flux components of every point; plus small
  * reduction scratch. */
 ATNS_API size_t at_workspace_bytes(const at_config* cfg);
 
@@ -119,7 +123,7 @@ ATNS_API int at_create(const at_config* cfg, void* dev_workspace, size_t ws_byte
 /* Load the state.  q_host: host float64 [n_levels][5][nz][ny][nx], oldest level first; the last
  * level becomes the current state Q^{n0}, n0 = n_levels - 1, and the older ones are published as
  * levels 0 .. n0 - 1 with synchronous derivatives (the synchronous start-up loop of Algs. SAA and
- * CAA fills L + t_l levels).  1 <= n_levels <= max_delay + 3.  Resets the step counter to n0, the
+ * CAA fills L + t_l levels).  1 <= n_levels <= max_delay + t_l.  Resets the step counter to n0, the
  * RK register and the conserved-total accumulators.  Errors: AT_E_INVAL, AT_E_HIP. */
 ATNS_API int at_init_field(at_sim* sim, const double* q_host, int32_t n_levels);
 
@@ -127,7 +131,7 @@ ATNS_API int at_init_field(at_sim* sim, const double* q_host, int32_t n_levels);
  * used by CAA (L must equal c_r - 1) and SAA; seed by SAA; table (host int8
  * [n_steps][p_x p_y p_z][6], PE index (tz p_y + ty) p_x + tx, faces -x,+x,-y,+y,-z,+z) by
  * EXPLICIT only (NULL otherwise).  Every entry must satisfy 0 <= k <= max_delay and, if k > 0,
- * n - k - 2 >= 0.  Errors: AT_E_INVAL, AT_E_SCHEDULE (entry invalid), AT_E_HIP. */
+ * n - k - (t_l - 1) >= 0.  Errors: AT_E_INVAL, AT_E_SCHEDULE (entry invalid), AT_E_HIP. */
 ATNS_API int at_set_delay_schedule(at_sim* sim, int32_t mode, int32_t L, int32_t c_r,
                                    uint64_t seed, const int8_t* table, int64_t n_steps);
 
@@ -147,7 +151,10 @@ ATNS_API int at_rhs(at_sim* sim, void* dev_out);
  * B = 1/3, 15/16, 8/15; c = 0, 1/3, 3/4).  Stage 1 of step n publishes level n.  A delayed face
  * (k >= 1) at stage s extrapolates levels n-k, n-k-1, n-k-2 to t_n + c_s dt with weights
  * w_0 = (kappa+1)(kappa+2)/2, w_1 = -kappa(kappa+2), w_2 = kappa(kappa+1)/2, kappa = k + c_s
- * (the Appendix B polynomials at c_s = 0); k = 0 reads the neighbour's current stage.
+ * (the Appendix B polynomials at c_s = 0); the sixth-order scheme extrapolates levels n-k .. n-k-3
+ * with w_0 = (kappa+1)(kappa+2)(kappa+3)/6, w_1 = -kappa(kappa+2)(kappa+3)/2,
+ * w_2 = kappa(kappa+1)(kappa+3)/2, w_3 = -kappa(kappa+1)(kappa+2)/6 (the (1,6) rows at c_s = 0);
+ * k = 0 reads the neighbour's current stage.
  * Asynchronous: returns after enqueueing.  Errors: AT_E_STATE, AT_E_SCHEDULE, AT_E_HIP. */
 ATNS_API int at_rk_step(at_sim* sim, int32_t n_steps);
 
@@ -197,7 +204,7 @@ ATNS_API int at_get_stage_tuning(at_sim* sim, int32_t* tile_sync, int32_t* zchun
  * recorded on the handle's stream; at_kernel_timing synchronises the stream and returns, for kernel
  * `kernel` (0 .. AT_N_KERNELS-1, named by at_kernel_name), the summed event time in ms and the
  * number of launches since timing was enabled.  Errors: AT_E_INVAL, AT_E_HIP. */
-#define AT_N_KERNELS 6
+#define AT_N_KERNELS 8
 ATNS_API int at_set_kernel_timing(at_sim* sim, int32_t enable);
 ATNS_API int at_kernel_timing(at_sim* sim, int32_t kernel, double* total_ms, int64_t* launches);
 ATNS_API const char* at_kernel_name(int32_t kernel);
@@ -246,7 +253,7 @@ ATNS_API int at_batch_create(int32_t precision, void* hip_stream, at_batch** out
 
 /* Add an initialised run (joins at its current step; members may be at different steps).
  * Errors: AT_E_INVAL (precision, stream or device differ; batch full; a forced run with a tile
- * shape that does not fit), AT_E_STATE (not initialised, already in a batch). */
+ * shape that does not fit; a sixth-order run), AT_E_STATE (not initialised, already in a batch). */
 ATNS_API int at_batch_add(at_batch* batch, at_sim* sim);
 
 /* Remove a member (it keeps its state and can be stepped alone).  Errors: AT_E_STATE. */

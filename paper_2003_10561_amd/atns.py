@@ -29,7 +29,7 @@ EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "a
             "at_batch_get_stage_tuning", "at_batch_autotune", "at_batch_set_graph",
             "at_batch_graph_stats", "at_batch_destroy", "at_serve", "at_field_stats_noalloc"]
 N_TILES = 7
-N_KERNELS = 6
+N_KERNELS = 8
 
 
 class AtError(RuntimeError):

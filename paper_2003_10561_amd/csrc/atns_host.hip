@@ -34,10 +34,13 @@ int validate(const at_config* c) {
   for (int d = 0; d < 3; ++d) {
     if (c->n[d] < 4 || c->p[d] < 1) return fail(AT_E_INVAL, "n[d] >= 4 and p[d] >= 1 required");
     if (c->n[d] % c->p[d]) return fail(AT_E_INVAL, "n[d] must be a multiple of p[d]");
-    if (c->n[d] / c->p[d] < 4) return fail(AT_E_INVAL, "PE edge n[d]/p[d] must be >= 4");
     if (c->n[d] > (1 << 14)) return fail(AT_E_INVAL, "n[d] too large");
   }
-  if (c->order != 4) return fail(AT_E_INVAL, "only order 4 is implemented");
+  if (c->order != 4 && c->order != 6) return fail(AT_E_INVAL, "order must be 4 or 6");
+  const int M = c->order / 2;
+  for (int d = 0; d < 3; ++d)
+    if (c->n[d] / c->p[d] < 2 * M) return fail(AT_E_INVAL, "PE edge n[d]/p[d] must be >= order");
+  if (c->order == 6 && c->forcing) return fail(AT_E_INVAL, "forcing is not implemented for the sixth-order scheme");
   if (c->max_delay < 0 || c->max_delay > kMaxDelay) return fail(AT_E_INVAL, "max_delay out of 0..8");
   if (c->precision != AT_FP64 && c->precision != AT_FP32) return fail(AT_E_INVAL, "bad precision");
   if (c->forcing != 0 && c->forcing != 1) return fail(AT_E_INVAL, "forcing must be 0 or 1");
@@ -45,8 +48,9 @@ int validate(const at_config* c) {
     // the stage kernel indexes fields and the ring with 32-bit element offsets
     const double npts = (double)c->n[0] * c->n[1] * c->n[2];
     double slab = 0.0;
-    for (int d = 0; d < 3; ++d) slab += 4.0 * c->p[d] * npts / c->n[d];
-    if (kNQ * npts >= 4294967296.0 || (c->max_delay + 3) * kNRing * slab >= 4294967296.0)
+    for (int d = 0; d < 3; ++d) slab += 2.0 * M * c->p[d] * npts / c->n[d];
+    if ((c->order == 6 ? 3 * kNQ : kNQ) * npts >= 4294967296.0 ||
+        (c->max_delay + M + 1) * kNRing * slab >= 4294967296.0)
       return fail(AT_E_INVAL, "grid too large for one handle (element offsets must stay below 2^32)");
   }
   if (!(c->gamma > 1.0) || !(c->gas_r > 0.0) || !(c->prandtl > 0.0) || !(c->t_ref > 0.0) ||
@@ -57,6 +61,9 @@ int validate(const at_config* c) {
 
 Geom make_geom(const at_config* c) {
   Geom g{};
+  g.order = c->order;
+  g.M = c->order / 2;
+  g.tl = g.M + 1;
   g.npts = 1;
   for (int d = 0; d < 3; ++d) {
     g.n[d] = c->n[d];
@@ -64,14 +71,14 @@ Geom make_geom(const at_config* c) {
     g.e[d] = c->n[d] / c->p[d];
     g.npts *= c->n[d];
   }
-  g.slab[0] = (int64_t)4 * c->p[0] * c->n[1] * c->n[2];
-  g.slab[1] = (int64_t)4 * c->p[1] * c->n[0] * c->n[2];
-  g.slab[2] = (int64_t)4 * c->p[2] * c->n[0] * c->n[1];
+  g.slab[0] = (int64_t)2 * g.M * c->p[0] * c->n[1] * c->n[2];
+  g.slab[1] = (int64_t)2 * g.M * c->p[1] * c->n[0] * c->n[2];
+  g.slab[2] = (int64_t)2 * g.M * c->p[2] * c->n[0] * c->n[1];
   g.ring_dir_off[0] = 0;
   g.ring_dir_off[1] = kNRing * g.slab[0];
   g.ring_dir_off[2] = kNRing * (g.slab[0] + g.slab[1]);
   g.ring_slot = kNRing * (g.slab[0] + g.slab[1] + g.slab[2]);
-  g.R = c->max_delay + 3;
+  g.R = c->max_delay + g.tl;
   g.ntiles = c->p[0] * c->p[1] * c->p[2];
   return g;
 }
@@ -95,9 +102,12 @@ Layout make_layout(const at_config* c, const Geom& g) {
   L.q[1] = take(kNQ * N * w);
   L.dq = take(kNQ * N * w);
   L.ring = take((size_t)g.R * g.ring_slot * w);
-  L.gv = take((size_t)3 * g.ring_slot * w);  // the AT sums of the three stages of a step
+  // the AT sums of the three stages of a step (fourth order); the flux buffer (sixth order)
+  L.gv = take(c->order == 4 ? (size_t)3 * g.ring_slot * w : 0);
+  L.flux = take(c->order == 6 ? (size_t)3 * kNQ * N * w : 0);
   // smallest tile (16 x 4) and smallest z chunk (4) bound the workgroup count of any stage launch
   L.ntot = (int64_t)((c->n[0] + 15) / 16) * ((c->n[1] + 3) / 4) * ((c->n[2] + 3) / 4);
+  if (c->order == 6) L.ntot = std::max<int64_t>(L.ntot, blocks6(g));
   L.tot_part = take((size_t)L.ntot * kNQ * 8);
   L.stat_part = take((size_t)stats_blocks(g) * kNStat * 8);
   L.stat_out = take(kStatOutBytes);
@@ -240,6 +250,41 @@ hipError_t launch_hooked(at_sim* s, const StageArgs<T>& a, int mode, bool at) {
   return e;
 }
 
+// Sixth-order stage arguments of run s at its current state and step.
+template <typename T>
+Stage6Args<T> base6(at_sim* s) {
+  Stage6Args<T> a{};
+  a.g = s->g;
+  a.cf = make_coef<T>(s);
+  for (int d = 0; d < 3; ++d) a.i60h[d] = a.cf.inv60h[d];
+  a.q = (T*)(s->ws + s->L.q[s->qcur]);
+  a.q_out = (T*)(s->ws + s->L.q[1 - s->qcur]);
+  a.dq = (T*)(s->ws + s->L.dq);
+  a.flux = (T*)(s->ws + s->L.flux);
+  a.ring = (T*)(s->ws + s->L.ring);
+  a.tot_part = (double*)(s->ws + s->L.tot_part);
+  tile6_of(s->g, &a.bx, &a.by);
+  a.delays = s->d_sched ? s->d_sched + (size_t)s->step * s->g.ntiles * 6 : s->d_zero;
+  a.step_mod_r = (int)(s->step % s->g.R);
+  a.mode = kModeStepH;
+  a.dt = (T)s->cfg.dt;
+  a.vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
+  return a;
+}
+
+// The two launches of one sixth-order stage (the second left out when only publishing).
+template <typename T>
+hipError_t launch6_hooked(at_sim* s, const Stage6Args<T>& a, bool div) {
+  if (s->timer) s->timer->before(kK6Grad, s->stream);
+  hipError_t e = launch_stage6<T>(a, true, s->stream);
+  if (s->timer) s->timer->after(kK6Grad, s->stream);
+  if (e != hipSuccess || !div) return e;
+  if (s->timer) s->timer->before(kK6Div, s->stream);
+  e = launch_stage6<T>(a, false, s->stream);
+  if (s->timer) s->timer->after(kK6Div, s->stream);
+  return e;
+}
+
 template <typename T>
 hipError_t launch_views(at_sim* s, const StageArgs<T>& a, int nst = 3) {
   if (s->timer) s->timer->before(kKGhost, s->stream);
@@ -270,7 +315,13 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
     HIP_TRY(hipMemcpyAsync(s->d_staging, q_host + (size_t)lev * kNQ * N, sizeof(double) * kNQ * N,
                            hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_convert<T>(s->d_staging, q, kNQ * N, s->stream));
-    if (lev < nlev - 1) {
+    if (lev < nlev - 1 && s->g.order == 6) {
+      Stage6Args<T> a = base6<T>(s);
+      a.delays = s->d_zero;
+      a.step_mod_r = (int)(lev % s->g.R);
+      a.publish = 1;
+      HIP_TRY(launch6_hooked<T>(s, a, false));
+    } else if (lev < nlev - 1) {
       // publish the history level with synchronous derivatives (all delays zero)
       StageArgs<T> a = base_args<T>(s);
       a.delays = s->d_zero;
@@ -295,8 +346,30 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
 }
 
 
+// Sixth-order RK3 steps: per stage the gradient / flux launch (publishing at stage 1) and the
+// divergence / update launch; delayed faces extrapolate to t_n + c_s dt.
+template <typename T>
+int do_steps6(at_sim* s, int nsteps) {
+  if (nsteps > 0) s->tot_used = std::max(s->tot_used, blocks6(s->g));
+  for (int it = 0; it < nsteps; ++it) {
+    for (int st = 0; st < 3; ++st) {
+      Stage6Args<T> a = base6<T>(s);
+      a.cs = (T)kRkC[st];
+      a.rk_a = (T)kRkA[st];
+      a.rk_b = (T)kRkB[st];
+      a.publish = st == 0;
+      a.store_dq = st < 2;
+      HIP_TRY(launch6_hooked<T>(s, a, true));
+      s->qcur = 1 - s->qcur;
+    }
+    s->step++;
+  }
+  return AT_OK;
+}
+
 template <typename T>
 int do_steps(at_sim* s, int nsteps) {
+  if (s->g.order == 6) return do_steps6<T>(s, nsteps);
   const size_t row = (size_t)s->g.ntiles * 6;
   if (nsteps > 0)
     s->tot_used = std::max({s->tot_used, fused_blocks(s->g, s->tile, s->zchunk), fused_blocks(s->g, s->tile_d, s->zchunk_d)});
@@ -336,6 +409,21 @@ int do_steps(at_sim* s, int nsteps) {
 // (the Runge-Kutta update with A = 0, B = 1).
 template <typename T>
 int do_ab2_steps(at_sim* s, int nsteps) {
+  if (s->g.order == 6) {
+    if (nsteps > 0) s->tot_used = std::max(s->tot_used, blocks6(s->g));
+    for (int it = 0; it < nsteps; ++it) {
+      Stage6Args<T> a = base6<T>(s);
+      a.rk_b = s->ab2_prev ? T(1.5) : T(1);
+      a.c_prev = s->ab2_prev ? T(-0.5) : T(0);
+      a.publish = 1;
+      a.store_dq = 1;
+      HIP_TRY(launch6_hooked<T>(s, a, true));
+      s->qcur = 1 - s->qcur;
+      s->ab2_prev = 1;
+      s->step++;
+    }
+    return AT_OK;
+  }
   const size_t row = (size_t)s->g.ntiles * 6;
   if (nsteps > 0)
     s->tot_used = std::max({s->tot_used, fused_blocks(s->g, s->tile, s->zchunk), fused_blocks(s->g, s->tile_d, s->zchunk_d)});
@@ -368,6 +456,13 @@ int do_ab2_steps(at_sim* s, int nsteps) {
 
 template <typename T>
 int do_rhs(at_sim* s, void* out) {
+  if (s->g.order == 6) {
+    Stage6Args<T> a = base6<T>(s);
+    a.mode = kModeRhsH;
+    a.rhs_out = (T*)out;
+    HIP_TRY(launch6_hooked<T>(s, a, true));
+    return AT_OK;
+  }
   StageArgs<T> a = base_args<T>(s);
   a.delays = s->d_sched + (size_t)s->step * s->g.ntiles * 6;
   a.step = s->step;
@@ -464,7 +559,7 @@ int at_create(const at_config* cfg, void* ws, size_t ws_bytes, void* stream, at_
 
 int at_init_field(at_sim* s, const double* q_host, int32_t n_levels) {
   if (!s || !q_host) return fail(AT_E_INVAL, "NULL argument");
-  if (n_levels < 1 || n_levels > s->g.R) return fail(AT_E_INVAL, "n_levels must be in 1 .. max_delay + 3");
+  if (n_levels < 1 || n_levels > s->g.R) return fail(AT_E_INVAL, "n_levels must be in 1 .. max_delay + t_l");
   return s->cfg.precision == AT_FP32 ? do_init<float>(s, q_host, n_levels) : do_init<double>(s, q_host, n_levels);
 }
 
@@ -478,13 +573,15 @@ int at_set_delay_schedule(at_sim* s, int32_t mode, int32_t L, int32_t c_r, uint6
     case AT_SYNC:
       break;
     case AT_CAA:
+      // synchronous for the first max(c_r, t_l) steps (the levels one extrapolation needs)
       if (c_r < 1 || L != c_r - 1) return fail(AT_E_INVAL, "CAA needs c_r >= 1 and L = c_r - 1");
-      for (int64_t n = c_r; n < n_steps; ++n)
+      for (int64_t n = std::max(c_r, s->g.tl); n < n_steps; ++n)
         std::memset(&t[(size_t)n * nt * 6], (int)(n % c_r), (size_t)nt * 6);
       break;
     case AT_SAA:
+      // synchronous for the first L + t_l steps (Alg. SAA)
       if (L < 0) return fail(AT_E_INVAL, "SAA needs L >= 0");
-      for (int64_t n = L + 3; n < n_steps; ++n)
+      for (int64_t n = L + s->g.tl; n < n_steps; ++n)
         for (int ti = 0; ti < nt; ++ti)
           for (int f = 0; f < 6; ++f) {
             const uint64_t ctr = ((uint64_t)n * nt + ti) * 6u + f;
@@ -502,7 +599,7 @@ int at_set_delay_schedule(at_sim* s, int32_t mode, int32_t L, int32_t c_r, uint6
   for (int64_t n = 0; n < n_steps; ++n)
     for (int i = 0; i < nt * 6; ++i) {
       const int k = t[(size_t)n * nt * 6 + i];
-      if (k < 0 || k > s->cfg.max_delay || (k > 0 && n - k - 2 < 0))
+      if (k < 0 || k > s->cfg.max_delay || (k > 0 && n - k - (s->g.tl - 1) < 0))
         return fail(AT_E_SCHEDULE, "schedule entry out of range or reads a level before 0");
     }
   if (s->d_sched) {

@@ -26,14 +26,17 @@ constexpr size_t kStatOutBytes = sizeof(double) * (kStatOutSlots + (size_t)kStat
 
 // Grid, virtual-PE tiling and ring geometry (shared by every kernel of one run).
 struct Geom {
+  int order;          // spatial order: 4 or 6
+  int M;              // layers each PE publishes per face (order / 2); the stencils' reach
+  int tl;             // levels of one AT extrapolation (M + 1)
   int n[3];           // points per direction
   int p[3];           // virtual PEs per direction
   int e[3];           // PE edge n[d] / p[d]
   int64_t npts;
-  int64_t slab[3];    // points of one direction's slab set: 4 p_d n_a n_b
+  int64_t slab[3];    // points of one direction's slab set: 2 M p_d n_a n_b
   int64_t ring_dir_off[3];  // element offset of direction d inside one ring slot
   int64_t ring_slot;  // elements per ring slot = 9 * sum_d slab[d]
-  int R;              // ring slots = max_delay + 3
+  int R;              // ring slots = max_delay + tl
   int ntiles;
 };
 
@@ -41,6 +44,7 @@ struct Geom {
 template <typename T>
 struct Coef {
   T inv12h[3];      // 1 / (12 h_d)
+  T inv60h[3];      // 1 / (60 h_d)
   T gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
 };
 
@@ -131,7 +135,36 @@ int64_t view_blocks(const Geom& g);  // 256-point blocks of k_at_sums for one ru
 constexpr int kModeStepH = 0, kModeRhsH = 1, kModePublishH = 2;
 
 // Kernel identities for timing (names in kernel_name()).
-enum KernelId { kKStage = 0, kKRhs = 1, kKPublish = 2, kKForce = 3, kKStats = 4, kKGhost = 5, kKCount = 6 };
+enum KernelId {
+  kKStage = 0, kKRhs = 1, kKPublish = 2, kKForce = 3, kKStats = 4, kKGhost = 5, kK6Grad = 6, kK6Div = 7,
+  kKCount = 8
+};
+
+// Sixth-order stage (stage6.hip): gradients and fluxes, then divergence and update; tiles of
+// bx x by columns inside one PE, one workgroup per (tile, z-PE).
+template <typename T>
+struct Stage6Args {
+  Geom g;
+  Coef<T> cf;
+  T i60h[3];
+  T* q;
+  T* q_out;
+  T* dq;
+  T* flux;            // [3][5][N]
+  T* ring;
+  T* rhs_out;
+  const int8_t* delays;
+  double* tot_part;
+  int bx, by;
+  int step_mod_r, publish, store_dq, mode;
+  T cs, rk_a, rk_b, dt, c_prev;
+  double vol;
+};
+void tile6_of(const Geom& g, int* bx, int* by);
+int64_t blocks6(const Geom& g);
+// gradflux: the gradient / flux launch; otherwise the divergence / update launch
+template <typename T>
+hipError_t launch_stage6(const Stage6Args<T>& s, bool gradflux, hipStream_t stream);
 const char* kernel_name(int id);
 
 // Optional event bracketing of each launch (host side implements it).
@@ -146,6 +179,7 @@ template <typename T>
 hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t stream);
 template <typename T>
 hipError_t launch_to_double(const T* src, double* dst, int64_t n, hipStream_t stream);
+// Statistics with the synchronous central derivatives of the run's order (g.order).
 template <typename T>
 hipError_t launch_stats(const Geom& g, const Coef<T>& cf, const T* q, double* part, double* out,
                         const double* tot_part, int64_t ntot_blocks, double gamma, hipStream_t stream,

@@ -36,8 +36,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Statistics partials per block with synchronous periodic derivatives (no PE faces).
-template <typename T>
+// Statistics partials per block with synchronous periodic derivatives (no PE faces) of the run's
+// order: the (1,4) central stencil (M = 2) or the (1,6) one (M = 3).
+template <typename T, int M>
 __global__ __launch_bounds__(256) void k_stats(Geom g, Coef<T> cf, const T* __restrict__ q,
                                                double* __restrict__ part) {
   const int x = blockIdx.x * kBX + threadIdx.x;
@@ -54,12 +55,12 @@ __global__ __launch_bounds__(256) void k_stats(Geom g, Coef<T> cf, const T* __re
     T G[kNGrad];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      T v[4][4];
-      const int ms[4] = {-2, -1, 1, 2};
+      T v[2 * M][4];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
+      for (int mi = 0; mi < 2 * M; ++mi) {
+        const int m = mi < M ? mi - M : mi - M + 1;
         int r[3] = {x, y, z};
-        r[d] = wrap1(pt[d] + ms[mi], g.n[d]);
+        r[d] = wrap1(pt[d] + m, g.n[d]);
         const int64_t ir = ((int64_t)r[2] * g.n[1] + r[1]) * g.n[0] + r[0];
         T pr[5];
         primitives<T>(q, N, ir, cf.inv_cv, pr);
@@ -69,8 +70,11 @@ __global__ __launch_bounds__(256) void k_stats(Geom g, Coef<T> cf, const T* __re
         v[mi][3] = pr[4];
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        G[c < 3 ? 3 * c + d : 9 + d] = (v[0][c] - T(8) * v[1][c] + T(8) * v[2][c] - v[3][c]) * cf.inv12h[d];
+      for (int c = 0; c < 4; ++c) {
+        const T num = M == 2 ? (v[0][c] - T(8) * v[1][c] + T(8) * v[2][c] - v[3][c])
+                             : (T(9) * v[1][c] - v[0][c]) + T(45) * (v[3][c] - v[2][c]) + (v[5][c] - T(9) * v[4][c]);
+        G[c < 3 ? 3 * c + d : 9 + d] = num * (M == 2 ? cf.inv12h[d] : cf.inv60h[d]);
+      }
     }
     T pr[5];
     primitives<T>(q, N, i, cf.inv_cv, pr);
@@ -262,7 +266,7 @@ int64_t stats_blocks(const Geom& g) { return update_blocks(g); }
 
 const char* kernel_name(int id) {
   static const char* names[kKCount] = {"k_stage", "k_stage(rhs)", "k_stage(publish)", "k_force_table",
-                                       "k_stats", "k_at_sums"};
+                                       "k_stats", "k_at_sums", "k6_gradflux", "k6_divupdate"};
   return (id >= 0 && id < kKCount) ? names[id] : "";
 }
 
@@ -292,7 +296,10 @@ hipError_t launch_stats(const Geom& g, const Coef<T>& cf, const T* q, double* pa
   (void)gamma;
   const dim3 blk(kBX, kBY, 1);
   const dim3 gr = grid_of(g);
-  HOOKED(kKStats, hipLaunchKernelGGL(k_stats<T>, gr, blk, 0, stream, g, cf, q, part));
+  if (g.order == 6)
+    HOOKED(kKStats, hipLaunchKernelGGL((k_stats<T, 3>), gr, blk, 0, stream, g, cf, q, part));
+  else
+    HOOKED(kKStats, hipLaunchKernelGGL((k_stats<T, 2>), gr, blk, 0, stream, g, cf, q, part));
   double* mid = out + kStatOutSlots;
   hipLaunchKernelGGL(k_stats_reduce, dim3(kStatRed), dim3(256), 0, stream, part, stats_blocks(g), tot_part,
                      ntot_blocks, mid);

@@ -29,7 +29,7 @@ inline size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Byte offsets of the workspace regions of one run.
 struct Layout {
-  size_t q[2], dq, ring, gv, tot_part, stat_part, stat_out, force_table, phase_x, phase_y, phase_z, total;
+  size_t q[2], dq, ring, gv, flux, tot_part, stat_part, stat_out, force_table, phase_x, phase_y, phase_z, total;
   int64_t ntot;  // FP64 total-accumulator slots (an upper bound on fused-stage workgroups)
 };
 
@@ -87,7 +87,10 @@ void batch_forget(at_batch* b, at_sim* s);
 template <typename T>
 Coef<T> coef_of(const at_config& c) {
   Coef<T> cf{};
-  for (int d = 0; d < 3; ++d) cf.inv12h[d] = (T)(1.0 / (12.0 * (kTwoPi / c.n[d])));
+  for (int d = 0; d < 3; ++d) {
+    cf.inv12h[d] = (T)(1.0 / (12.0 * (kTwoPi / c.n[d])));
+    cf.inv60h[d] = (T)(1.0 / (60.0 * (kTwoPi / c.n[d])));
+  }
   const double cv = c.gas_r / (c.gamma - 1.0);
   const double cp = c.gamma * c.gas_r / (c.gamma - 1.0);
   cf.gas_r = (T)c.gas_r;

@@ -59,7 +59,19 @@ def test_workspace_bytes_formula(lib):
     assert need <= b64 <= 1.1 * need
 
 
-@pytest.mark.parametrize("bad", [dict(n=(30, 32, 32), p=(4, 2, 1)), dict(p=(16, 2, 1)), dict(order=6),
+def test_workspace_bytes_formula_order6(lib):
+    """Sixth order: three face layers per side (phi = 6 (1/ex + 1/ey + 1/ez)), a ring of L + 4 levels
+    and the 15-component flux buffer instead of the AT-sum buffers."""
+    b64 = atns.workspace_bytes(cfg(order=6))
+    N = 32 ** 3
+    phi = 6 * (1 / 16 + 1 / 16 + 1 / 32)
+    ring = (3 + 4) * 9 * phi * N
+    need = 8 * (5 + 5 + 5 + 15) * N + 8 * ring
+    assert need <= b64 <= 1.1 * need
+
+
+@pytest.mark.parametrize("bad", [dict(n=(30, 32, 32), p=(4, 2, 1)), dict(p=(16, 2, 1)), dict(order=8),
+                                 dict(order=6, p=(8, 2, 1)), dict(order=6, forcing=True),
                                  dict(max_delay=9), dict(dt=0.0), dict(mu_ref=-1.0),
                                  dict(gamma=1.0), dict(precision="fp16x")])
 def test_invalid_config_rejected_without_gpu(lib, bad):
