@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cfg2", action="store_true", help="skip the decaying 256^3 FP64 configuration")
+    ap.add_argument("--no-order6", action="store_true", help="skip the sixth-order scheme")
     ap.add_argument("--cfg2-steps", type=int, default=100)
     ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
     ap.add_argument("--zchunk", type=int, default=None)
@@ -121,20 +122,22 @@ def kernel_window(torch, sim, steps, step_fn=None):
 STAGE_KERNELS = ("k_stage", "k_at_sums")
 
 
-def roofline(kt, n, pe, word, pd, steps):
+def roofline(kt, n, pe, word, pd, steps, kernels=STAGE_KERNELS, order=4):
     """Dominant launch = one RK stage: the fused stage kernel plus, at delayed steps, the AT sums it
-    reads (the method's delayed-level reads).  Algorithmic bytes per stage launch (the minimal count
+    reads (the method's delayed-level reads); for the sixth-order scheme the gradient / flux and the
+    divergence / update launches of a stage.  Algorithmic bytes per stage launch (the minimal count
     of traffic.words_per_point_step, a third of a step's) over the average event-timed duration of
     those kernels per stage."""
     from paper_2003_10561_amd import traffic
-    stage_kernels = [k for k in kt if k in STAGE_KERNELS]
+    stage_kernels = [k for k in kt if k in kernels]
     launches = steps * 3
     stage_ms = sum(kt[k][0] for k in stage_kernels) / launches
-    words = traffic.words_per_point_step((n,) * 3, (pe,) * 3, pd) / 3.0
+    words = traffic.words_per_point_step((n,) * 3, (pe,) * 3, pd, order) / 3.0
     bytes_per_launch = words * word * n ** 3
     achieved = bytes_per_launch / (stage_ms * 1e-3) / 1e9
     name = "+".join(stage_kernels)
-    loose = traffic.words_per_point_step_stage_reads((n,) * 3, (pe,) * 3, pd) * word
+    loose = (traffic.words_per_point_step_stage_reads((n,) * 3, (pe,) * 3, pd) * word if order == 4
+             else words * 3 * word)
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": stage_ms,
@@ -194,6 +197,17 @@ def batch_specs(seed0=1000):
     return specs
 
 
+def _run_delayed_fraction(sp, first, steps):
+    """Delayed fraction of a batched run's (step, face) pairs over steps [first, first + steps): exact
+    for periodic delays (every face at n mod c_r after c_r warm-up steps), the expectation L / (L + 1)
+    after the L + 3 warm-up steps for random ones."""
+    L = sp["L"]
+    rng = range(first, first + steps)
+    if sp["mode"] == "caa":
+        return sum(1 for n in rng if n >= L + 1 and n % (L + 1) != 0) / steps
+    return sum(L / (L + 1) for n in rng if n >= L + 3) / steps
+
+
 def batched_workload(torch, atns, W, steps, warmup, cache):
     specs = batch_specs()
     sims = []
@@ -227,6 +241,11 @@ def batched_workload(torch, atns, W, steps, warmup, cache):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
     pts = sum(sp["n"] ** 3 for sp in specs)
+    from paper_2003_10561_amd import traffic
+    step_bytes = sum(4 * sp["n"] ** 3 * traffic.words_per_point_step((sp["n"],) * 3, (sp["p"],) * 3,
+                                                                     _run_delayed_fraction(sp, warmup, steps))
+                     for sp in specs)
+    gbs = step_bytes / (ms / steps * 1e-3) / 1e9
     caps, reps = b.graph_stats()
     nonfinite = sum(s.stats()["nonfinite"] for s in sims)
     b.close()
@@ -236,6 +255,9 @@ def batched_workload(torch, atns, W, steps, warmup, cache):
             "steps": steps, "warmup": warmup, "ms_per_step": ms / steps, "tile": tile, "zchunk": zc,
             "tile_delayed": tile_d, "zchunk_delayed": zc_d,
             "autotune_stage_ms": tune_ms, "graph_captures": caps, "graph_replays": reps,
+            "roofline": {"bound": "hbm", "kernel": "batched step (all launches)", "achieved": gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_step": step_bytes},
             "nonfinite_runs": int(nonfinite),
             "workload": "64 runs (16 each of 32^3, 64^3, 96^3, 128^3), CAA/SAA L in 1..3, FP32, one batched "
                         "launch per kernel per RK stage from a HIP graph"}
@@ -268,10 +290,14 @@ def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64, tile_delayed=-
                                zchunk=zchunk, tile_delayed=tile_delayed, zchunk_delayed=zchunk_delayed)
     ok = [o for o in res if o["status"] == 0]
     lat = np.array([o["done_s"] - r["arrival_s"] for r, o in zip(reqs, res) if o["status"] == 0])
+    queue = np.array([o["admit_s"] - r["arrival_s"] for r, o in zip(reqs, res) if o["status"] == 0])
+    service = np.array([o["done_s"] - o["admit_s"] for o in res if o["status"] == 0])
     work = sum(r["n"] ** 3 * r["steps"] for r, o in zip(reqs, res) if o["status"] == 0)
     offered = sum(r["n"] ** 3 * r["steps"] for r in reqs) / seconds
     return {"requests": len(reqs), "served": len(ok), "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "throughput": work / makespan,
+            "p50_queue_s": float(np.percentile(queue, 50)), "p99_queue_s": float(np.percentile(queue, 99)),
+            "p50_service_s": float(np.percentile(service, 50)), "p99_service_s": float(np.percentile(service, 99)),
             "unit": "grid-pt-steps/s", "offered_load": offered, "makespan_s": makespan,
             "arrival_window_s": seconds, "nonfinite": int(sum(o["stats"]["nonfinite"] for o in ok)),
             "tile": tile, "zchunk": zchunk, "tile_delayed": tile_delayed, "zchunk_delayed": zchunk_delayed,
@@ -337,6 +363,28 @@ def cpu_baseline(W, n, steps):
 def field_rel_l2(a, b):
     """Relative L2 error of each conserved component of a against b."""
     return [float(np.linalg.norm((a[c] - b[c]).ravel()) / np.linalg.norm(b[c].ravel())) for c in range(a.shape[0])]
+
+
+def order6_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K):
+    """The sixth-order AT scheme ((1,6) rows, 4-level extrapolation) on the same 512^3 field, FP32,
+    unforced (decaying), CAA c_r = 4: timed window, then a kernel-event window for the roofline of
+    its two launches per stage."""
+    total = Wm + 2 * K + 2
+    cfg = atns.Config(n=(n,) * 3, p=(pe,) * 3, dt=dt, mu_ref=mu, max_delay=3, precision="fp32", order=6)
+    sim = atns.Sim(cfg)
+    sim.init_field(q)
+    sim.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=total)
+    ms = time_window(torch, sim, K, warmup=Wm)
+    ms_ev, kt = kernel_window(torch, sim, K)
+    st = sim.stats()
+    sim.close()
+    torch.cuda.empty_cache()
+    pd = sum(1 for s in range(Wm + K, Wm + 2 * K) if s >= 4 and s % 4) / K
+    rf = roofline(kt, n, pe, 4, pd, K, kernels=("k6_gradflux", "k6_divupdate"), order=6)
+    return {"value": n ** 3 * K / (ms * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms / K, "steps": K,
+            "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items()}, "roofline": rf,
+            "delayed_fraction": pd, "nonfinite": st["nonfinite"],
+            "workload": f"decaying turbulence {n}^3, {pe}x{pe}x{pe} PEs, sixth-order AT scheme, CAA L=3, FP32"}
 
 
 def decaying_cfg2(torch, atns, W, traffic, steps):
@@ -494,6 +542,10 @@ def main():
                                                   for k in ("K", "eps", "enstrophy", "Mt")},
                        "error_note": f"FP32 and FP64 runs after the same {Wm + 2 * K} RK3 steps; the FP64 path "
                                      "matches the FP64 oracle at this size"}
+    if not args.no_order6:
+        log("sixth-order scheme ...")
+        out["order6"] = order6_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K)
+        log(f"order6: {out['order6']}")
     if not args.no_cfg2:
         log("decaying 256^3 FP64 configuration ...")
         out["decaying_256"] = decaying_cfg2(torch, atns, W, traffic, args.cfg2_steps)

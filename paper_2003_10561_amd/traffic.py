@@ -17,14 +17,17 @@ roofline fraction.
 from __future__ import annotations
 
 
-def ghost_fraction(n, p) -> float:
-    return sum(4.0 * p[d] / n[d] for d in range(3))
+def ghost_fraction(n, p, order: int = 4) -> float:
+    """Fraction of points on published face layers: 2 M (1/ex + 1/ey + 1/ez), M = order / 2."""
+    return sum(order * p[d] / n[d] for d in range(3))
 
 
-def words_per_point_step(n, p, p_delayed: float) -> float:
-    """Minimal words per point-step of an RK3 step (delayed levels read once per step)."""
-    phi = ghost_fraction(n, p)
-    return 50.0 + 9.0 * phi + 27.0 * phi * p_delayed
+def words_per_point_step(n, p, p_delayed: float, order: int = 4) -> float:
+    """Minimal words per point-step of an RK3 step (delayed levels read once per step; the
+    sixth-order scheme extrapolates from t_l = 4 levels instead of 3)."""
+    phi = ghost_fraction(n, p, order)
+    tl = order // 2 + 1
+    return 50.0 + 9.0 * phi + 9.0 * tl * phi * p_delayed
 
 
 def words_per_point_step_stage_reads(n, p, p_delayed: float) -> float:

@@ -105,3 +105,31 @@ def test_decaying_fp64_256_saa_stats_every_step():
     check_fields(g.get_field(), o.field(), 1e-12, f"fp64 after {steps} steps")
     g.close()
     torch.cuda.empty_cache()
+
+
+def test_order6_bench_pe_shape_fp64_fp32_caa():
+    """The sixth-order scheme in the PE shape of the 512^3 benchmark leg: 128^3 on 2x2x2 PEs of 64^3
+    (32x8-column tiles), unforced, CAA c_r = 4, eight steps (delays 1, 2, 3 reached, the seven-slot
+    ring wrapping): FP64 fields and statistics within 1e-12 of the oracle, FP32 fields within 2e-6."""
+    n, pe, steps = 128, 2, 8
+    say(f"case order-6 {n}^3 on {pe}^3 PEs of 64^3, CAA c_r=4, {steps} steps, fp64 and fp32")
+    q = W.make_field(n, 3, 0.3)
+    dt, mu = W.default_dt(q), W.default_mu(n)
+    got = {}
+    for prec in ("fp64", "fp32"):
+        g = atns.Sim(atns.Config(n=(n,) * 3, p=(pe,) * 3, dt=dt, mu_ref=mu, max_delay=3, precision=prec, order=6))
+        g.init_field(q)
+        g.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=steps + 1)
+        g.rk_step(steps)
+        got[prec] = (g.get_field(), g.stats())
+        g.close()
+    o = Oracle(OracleConfig(n=(n,) * 3, p=(pe,) * 3, dt=dt, mu_ref=mu, max_delay=3, order=6))
+    o.init_field(q)
+    o.set_schedule(atns.CAA, L=3, c_r=4, n_steps=steps + 1)
+    for s in range(steps):
+        o.rk_step(1)
+        say(f"  oracle step {s + 1}/{steps}")
+    ref = o.field()
+    check_fields(got["fp64"][0], ref, 1e-12, f"fp64 after {steps} steps")
+    check_stats(got["fp64"][1], o.stats(), 1e-12)
+    check_fields(got["fp32"][0], ref, 2e-6, f"fp32 after {steps} steps")
