@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the served request trace")
     ap.add_argument("--no-ab2", action="store_true", help="skip the Adams-Bashforth steps after the timed RK3 steps")
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the Poisson arrival window")
+    ap.add_argument("--serve-seconds", type=float, default=100.0, help="length of the Poisson arrival window")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON lines)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")

@@ -123,7 +123,9 @@ ATNS_API int at_create(const at_config* cfg, void* dev_workspace, size_t ws_byte
 /* Load the state.  q_host: host float64 [n_levels][5][nz][ny][nx], oldest level first; the last
  * level becomes the current state Q^{n0}, n0 = n_levels - 1, and the older ones are published as
  * levels 0 .. n0 - 1 with synchronous derivatives (the synchronous start-up loop of Algs. SAA and
- * CAA fills L + t_l levels).  1 <= n_levels <= max_delay + t_l.  Resets the step counter to n0, the
+ * CAA fills L + t_l levels).  1 <= n_levels <= max_delay + t_l.  q_host is copied before the call
+ * returns; the device work (conversion, publication, the initial conserved totals) is enqueued on
+ * the stream without waiting for it.  Resets the step counter to n0, the
  * RK register and the conserved-total accumulators.  Errors: AT_E_INVAL, AT_E_HIP. */
 ATNS_API int at_init_field(at_sim* sim, const double* q_host, int32_t n_levels);
 
@@ -297,12 +299,14 @@ ATNS_API int at_batch_destroy(at_batch* batch);
 /* ---------------------------------------------------------------------------------------------
  * Served runs (continuous batching).  at_serve replays a request trace against the wall clock:
  * a request becomes visible at its arrival time, is admitted first come first served when fewer
- * than max_active runs are active and its device footprint (workspace, staging, schedule) fits
- * both the HBM budget and the free device memory, joins the batch at the next step boundary,
- * and leaves at the boundary where it has done its steps, after its final statistics (and field,
- * if asked) are read back.  The batch advances by the fewest steps any active run has left, at
- * most 8, between admissions.  The server allocates and frees the workspaces itself.  Unforced cubes
- * only; each request's delays are AT_SYNC, AT_CAA (c_r = L + 1) or AT_SAA (seed).
+ * than max_active runs are admitted and its device footprint (workspace, staging, schedule) fits
+ * the HBM budget (capped by the device memory free when serving starts, less 1 GiB), is prepared
+ * on a second stream while the batch computes (handle, field upload and conversion, schedule),
+ * joins the batch at the next step boundary, and leaves at the boundary where it has done its
+ * steps, after its final statistics (and field, if asked) are read back.  The batch advances by the
+ * fewest steps any active run has left, at most 8, between boundaries.  The server allocates the
+ * workspaces itself, reuses those of finished runs and frees them at the end.  Unforced
+ * fourth-order cubes only; each request's delays are AT_SYNC, AT_CAA (c_r = L + 1) or AT_SAA (seed).
  * ------------------------------------------------------------------------------------------- */
 typedef struct {
   int32_t precision;        /* AT_FP32 | AT_FP64 */
@@ -325,7 +329,8 @@ typedef struct {
 } at_request;
 
 typedef struct {
-  double admit_s, done_s;   /* seconds after the start: admission, completion (stats read back) */
+  double admit_s, done_s;   /* seconds after the start: admission (preparation begins), completion */
+                            /* (statistics read back)                                            */
   at_stats_t stats;         /* final statistics */
   int32_t status;           /* AT_OK, or the error that ended this request */
   int32_t reserved;

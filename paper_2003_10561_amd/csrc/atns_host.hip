@@ -301,8 +301,11 @@ int do_stats(at_sim* s, double* host_out) {
   HIP_TRY(launch_stats<T>(s->g, cf, (const T*)(s->ws + s->L.q[s->qcur]), part, out,
                           (const double*)(s->ws + s->L.tot_part), s->tot_used, s->cfg.gamma,
                           s->stream, s->timer));
-  HIP_TRY(hipMemcpyAsync(host_out, out, (kNStat + kNQ) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (host_out) {
+    // the statistics, the RK totals and the initial totals (kStatInit) in one copy
+    HIP_TRY(hipMemcpyAsync(host_out, out, (kStatInit + kNQ) * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
   return AT_OK;
 }
 
@@ -334,11 +337,11 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
   HIP_TRY(hipMemsetAsync(s->ws + s->L.dq, 0, sizeof(T) * kNQ * N, s->stream));
   HIP_TRY(hipMemsetAsync(s->ws + s->L.tot_part, 0, sizeof(double) * kNQ * s->L.ntot, s->stream));
   s->tot_used = 0;
-  double st[kNStat + kNQ];
-  int rc = do_stats<T>(s, st);
+  // the initial totals stay on the device (read with the statistics): no synchronisation here
+  int rc = do_stats<T>(s, nullptr);
   if (rc) return rc;
-  const double vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
-  for (int c = 0; c < kNQ; ++c) s->tot_init[c] = st[c] * vol;
+  double* out = (double*)(s->ws + s->L.stat_out);
+  HIP_TRY(hipMemcpyAsync(out + kStatInit, out, kNQ * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
   s->step = nlev - 1;
   s->ab2_prev = 0;
   s->initialised = 1;
@@ -666,20 +669,22 @@ int at_ab2_step(at_sim* s, int32_t n_steps) {
 int at_stats(at_sim* s, at_stats_t* out) {
   if (!s || !out) return fail(AT_E_INVAL, "NULL argument");
   if (!s->initialised) return fail(AT_E_STATE, "at_init_field first");
-  double st[kNStat + kNQ];
+  double st[kStatInit + kNQ];
   int rc = s->cfg.precision == AT_FP32 ? do_stats<float>(s, st) : do_stats<double>(s, st);
   if (rc) return rc;
   const double N = (double)s->g.npts;
   const double vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
+  double tot_init[kNQ];
+  for (int c = 0; c < kNQ; ++c) tot_init[c] = st[kStatInit + c] * vol;
   std::memset(out, 0, sizeof(*out));
   out->step = s->step;
   out->time = (double)s->step * s->cfg.dt;
   out->mass = st[0] * vol;
   for (int a = 0; a < 3; ++a) out->mom[a] = st[1 + a] * vol;
   out->energy = st[4] * vol;
-  out->mass_rk = s->tot_init[0] + st[kNStat + 0];
-  for (int a = 0; a < 3; ++a) out->mom_rk[a] = s->tot_init[1 + a] + st[kNStat + 1 + a];
-  out->energy_rk = s->tot_init[4] + st[kNStat + 4];
+  out->mass_rk = tot_init[0] + st[kNStat + 0];
+  for (int a = 0; a < 3; ++a) out->mom_rk[a] = tot_init[1 + a] + st[kNStat + 1 + a];
+  out->energy_rk = tot_init[4] + st[kNStat + 4];
   out->K = st[5] / N;
   out->eps = st[6] / N;
   out->enstrophy = st[7] / N;

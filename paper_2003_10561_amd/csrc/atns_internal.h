@@ -21,6 +21,9 @@ constexpr int kMaxDelay = 8;
 // Statistics output region: 18 doubles (13 statistics, 5 RK totals) in the first kStatOutSlots,
 // then the kStatRed level-1 rows of the two-level reduction.
 constexpr int kStatOutSlots = 32;
+// Slots kStatInit .. kStatInit + 4 of the output region keep the FP64 sums of the conserved
+// variables of the state loaded by at_init_field (the start of the RK-accumulated totals).
+constexpr int kStatInit = 24;
 constexpr int kStatRed = 256;
 constexpr size_t kStatOutBytes = sizeof(double) * (kStatOutSlots + (size_t)kStatRed * (kNStat + 5));
 

@@ -64,7 +64,6 @@ struct at_sim {
   int zchunk = 64;              // the stages that read no delayed level
   int tile_d = 1;               // the same for the stages that read delayed levels
   int zchunk_d = 64;
-  double tot_init[atns::kNQ];
   int64_t tot_used = 0;               // FP64 total slots written by stage launches so far
   int ab2_prev = 0;                   // the RK register holds dt f^{n-1} of an Adams-Bashforth step
   atns::EventTimer* timer = nullptr;  // non-null while kernel timing is enabled
