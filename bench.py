@@ -146,17 +146,17 @@ def roofline(kt, n, pe, word, pd, steps, kernels=STAGE_KERNELS, order=4):
             "frac_stage_reads": loose / 3.0 * n ** 3 / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def stage_source_sha():
+def stage_source_sha(source="stage_fused.hip"):
     import hashlib
-    src = os.path.join(ROOT, "paper_2003_10561_amd", "csrc", "stage_fused.hip")
+    src = os.path.join(ROOT, "paper_2003_10561_amd", "csrc", source)
     with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(n, pe, precision):
-    """HBM bytes per stage launch from the committed counter summary, if it was taken on the
-    current stage-kernel source for this workload; otherwise None."""
-    path = os.path.join(ROOT, "profiles", f"k_stage_{n}_pe{pe}_{precision}_traffic.md")
+def measured_traffic(name, source="stage_fused.hip"):
+    """HBM bytes per stage from the committed counter summary profiles/<name>_traffic.md, if it was
+    taken on the current source of the kernels it covers; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.md")
     # written by paper_2003_10561_amd/profsum.py from FETCH_SIZE / WRITE_SIZE runs of this bench
     if not os.path.exists(path):
         return None
@@ -166,7 +166,7 @@ def measured_traffic(n, pe, precision):
             m = re.match(r"^- (\w+): (\S+)\s*$", line)
             if m:
                 kv[m.group(1)] = m.group(2)
-    if kv.get("source_sha256") != stage_source_sha() or "bytes_per_launch" not in kv:
+    if kv.get("source_sha256") != stage_source_sha(source) or "bytes_per_launch" not in kv:
         return None
     return float(kv["bytes_per_launch"])
 
@@ -381,6 +381,7 @@ def order6_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K):
     torch.cuda.empty_cache()
     pd = sum(1 for s in range(Wm + K, Wm + 2 * K) if s >= 4 and s % 4) / K
     rf = roofline(kt, n, pe, 4, pd, K, kernels=("k6_gradflux", "k6_divupdate"), order=6)
+    rf["traffic"] = measured_traffic(f"k6_stage_{n}_pe{pe}_fp32", "stage6.hip")
     return {"value": n ** 3 * K / (ms * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms / K, "steps": K,
             "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items()}, "roofline": rf,
             "delayed_fraction": pd, "nonfinite": st["nonfinite"],
@@ -488,7 +489,7 @@ def main():
     torch.cuda.empty_cache()
     log(f"fp32: {ms32 / K:.3f} ms/step ({ms32_ev / K:.3f} with kernel events); kernels {kt32}")
     rf = roofline(kt32, n, pe, 4, pd_k, K)
-    rf["traffic"] = measured_traffic(n, pe, "fp32")
+    rf["traffic"] = measured_traffic(f"k_stage_{n}_pe{pe}_fp32")
     value = n ** 3 * K / (ms32 * 1e-3)
     out = {"metric": METRIC, "value": value, "unit": "grid-pt-steps/s", "n_gpus": 1, "steps": K,
            "warmup": Wm, "ms_per_step": ms32 / K, "higher_is_better": True, "scaling": "weak",
@@ -531,10 +532,12 @@ def main():
         log(f"fp64: {ms64 / K:.3f} ms/step")
         v64 = n ** 3 * K / (ms64 * 1e-3)
         rf64 = roofline(kt64, n, pe, 8, pd_k, K)
+        rf64["traffic"] = measured_traffic(f"k_stage_{n}_pe{pe}_fp64")
         errs = field_rel_l2(f32, f64)
         del f32, f64
         out["fp64"] = {"value": v64, "ms_per_step": ms64 / K, "roofline_frac": rf64["frac"], "launch": launch64,
                        "achieved_gbs": rf64["achieved"], "avg_launch_ms": rf64["avg_launch_ms"],
+                       "roofline": rf64,
                        "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 8) * v64 / 1e9,
                        "fp32_speedup": value / v64,
                        "fp32_vs_fp64_field_rel_l2": dict(zip(("rho", "rho_u", "rho_v", "rho_w", "E"), errs)),

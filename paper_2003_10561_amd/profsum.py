@@ -11,6 +11,11 @@ bench command, plus the same two counters for a plain device copy of known size,
 
 Usage: python -m paper_2003_10561_amd.profsum --trace DIR --fetch DIR --write DIR --copy-fetch DIR
        --copy-write DIR --copy-bytes B --timed 30 --out profiles/k_stage_512_pe8_fp32 --command "..."
+       [--stage k_stage< --aux k_at_sums<]
+
+--stage names the launch that ends each RK stage (one per stage), --aux the launches that belong to
+the stage before it (the AT sums of the fourth-order scheme; the gradient / flux launch of the
+sixth-order one, whose divergence / update launch is the stage launch).
 """
 from __future__ import annotations
 
@@ -21,7 +26,7 @@ import hashlib
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STAGE = "k_stage<"
+STAGE = "k_stage<"  # defaults; main() takes --stage / --aux
 VIEWS = "k_at_sums<"
 
 
@@ -51,12 +56,12 @@ def counters(pmc_dir):
 
 
 def timed_window(seq, timed):
-    """Entries from the `timed`-th last stage launch on (its AT-sum launch included)."""
+    """Entries from the `timed`-th last stage launch on (the auxiliary launches before it included)."""
     idx = [i for i, (k, _) in enumerate(seq) if STAGE in k]
     if len(idx) < timed:
         raise ValueError(f"only {len(idx)} stage launches")
     first = idx[-timed]
-    # the AT sums of a delayed stage are launched just before its stage launch
+    # the auxiliary launches of a stage come just before its stage launch
     while first > 0 and VIEWS in seq[first - 1][0]:
         first -= 1
     last = idx[-1]
@@ -69,8 +74,11 @@ def copy_factor(pmc_dir, nbytes):
     return nbytes / (big * 1024.0)
 
 
+SOURCE = "stage_fused.hip"
+
+
 def source_sha():
-    with open(os.path.join(HERE, "csrc", "stage_fused.hip"), "rb") as f:
+    with open(os.path.join(HERE, "csrc", SOURCE), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
 
@@ -81,7 +89,12 @@ def main():
     ap.add_argument("--copy-bytes", type=float, required=True)
     ap.add_argument("--timed", type=int, required=True)
     ap.add_argument("--workload", default="")
+    ap.add_argument("--stage", default="k_stage<")
+    ap.add_argument("--aux", default="k_at_sums<")
+    ap.add_argument("--source", default="stage_fused.hip", help="kernel source whose sha256 is recorded")
     a = ap.parse_args()
+    global STAGE, VIEWS, SOURCE
+    STAGE, VIEWS, SOURCE = a.stage, a.aux, a.source
 
     seq = dispatches(a.trace)
     win = timed_window(seq, a.timed)
@@ -98,7 +111,7 @@ def main():
             rows.append(f"| `{short_name(k)[:80]}` | {c} | {t / c:.3f} | {t:.1f} |")
         return rows
 
-    lines = [f"# Kernel trace: stage kernels, {a.workload}", "",
+    lines = [f"# Kernel trace: {STAGE.rstrip('<')} and {VIEWS.rstrip('<')}, {a.workload}", "",
              "Command (R = the repository root; run from /tmp with `export TMPDIR=/tmp`):", "",
              "```", a.command.split(" ;; ")[0], "```", "",
              f"Kernels of the timed window (the last {a.timed} stage launches of the single-run workload):", ""]
@@ -106,9 +119,11 @@ def main():
     lines += ["", "Whole run, the 12 kernels with the most time (other workloads of the command included):", ""]
     lines += table(seq, 12)
     lines += ["", f"Timed window (last {a.timed} stage launches):", "",
-              f"- k_stage_avg_ms: {st_ms / a.timed:.4f}",
-              f"- k_at_sums_launches: {n_gv}",
-              f"- k_at_sums_ms_per_stage: {gv_ms / a.timed:.4f}",
+              f"- stage_launch: {STAGE.rstrip('<')}",
+              f"- aux_launch: {VIEWS.rstrip('<')}",
+              f"- stage_launch_avg_ms: {st_ms / a.timed:.4f}",
+              f"- aux_launches: {n_gv}",
+              f"- aux_ms_per_stage: {gv_ms / a.timed:.4f}",
               f"- stage_avg_ms: {(st_ms + gv_ms) / a.timed:.4f}",
               f"- source_sha256: {source_sha()}", ""]
     with open(a.out + "_trace.md", "w") as f:
@@ -123,21 +138,21 @@ def main():
     sf = [v * 1024.0 * ff for k, v in fetch if STAGE in k]
     sw = [v * 1024.0 * fw for k, v in write if STAGE in k]
     cmds = a.command.split(" ;; ")
-    lines = [f"# HBM traffic: stage kernels, {a.workload}", "",
+    lines = [f"# HBM traffic: {STAGE.rstrip('<')} and {VIEWS.rstrip('<')}, {a.workload}", "",
              "Commands (R = the repository root; run from /tmp with `export TMPDIR=/tmp`):", "", "```"]
     lines += cmds[1:] if len(cmds) > 1 else cmds
     lines += ["```", "",
               f"Copy calibration: for a device copy of {a.copy_bytes:.0f} bytes each way, bytes moved / "
               f"bytes reported is {ff:.4f} for FETCH_SIZE and {fw:.4f} for WRITE_SIZE; these factors scale "
               "the stage counters below.", "",
-              "Per stage launch over the timed window (k_stage plus the AT sums of delayed stages):", "",
+              f"Per stage over the timed window ({STAGE.rstrip('<')} plus {VIEWS.rstrip('<')}):", "",
               f"- fetch_bytes_per_launch: {fb:.6e}",
               f"- write_bytes_per_launch: {wb:.6e}",
               f"- bytes_per_launch: {fb + wb:.6e}",
               f"- fetch_scale: {ff:.6f}",
               f"- write_scale: {fw:.6f}",
               f"- source_sha256: {source_sha()}", "",
-              "k_stage alone, per launch in the window (GB fetched / written):", "",
+              f"{STAGE.rstrip('<')} alone, per launch in the window (GB fetched / written):", "",
               "| launch | fetch GB | write GB |", "|---|---|---|"]
     for i, (x, y) in enumerate(zip(sf, sw)):
         lines.append(f"| {i} | {x / 1e9:.3f} | {y / 1e9:.3f} |")
