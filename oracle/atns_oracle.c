@@ -733,6 +733,40 @@ int ora_rhs_periodic_standard(const ora_config* cfg, const double* q, double* ou
   return ORA_OK;
 }
 
+/* Point fields behind the turbulence statistics of Sec. 4.1, with the synchronous central
+ * derivatives of the run's order on the periodic grid (the derivatives ora_stats uses): out
+ * [7][N] = u, v, w, p = rho R T, du/dx, the dissipation sigma_ij du_i/dx_j and |curl u|^2 --
+ * the per-point terms whose means are <eps> and Omega in ora_stats. */
+int ora_diag_fields(const ora_config* cfg, const double* q, double* out) {
+  if (!cfg || !q || !out) return ORA_E_INVAL;
+  ora_config c = *cfg;
+  c.p[0] = c.p[1] = c.p[2] = 1;
+  c.forcing = 0;
+  ora_sim* s;
+  int rc = ora_create(&c, &s);
+  if (rc) return rc;
+  const int64_t N = s->npts;
+  compute_primitives(s, q);
+  compute_gradients(s, 0, 1);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; i++) {
+    double G[NG], sig[9], kt;
+    for (int g = 0; g < NG; g++) G[g] = s->grad[(int64_t)g * N + i];
+    const double rho = s->prim[i], T = s->prim[4 * N + i];
+    for (int a = 0; a < 3; a++) out[a * N + i] = s->prim[(1 + a) * N + i];
+    out[3 * N + i] = rho * c.gas_r * T;
+    out[4 * N + i] = G[0];
+    stress(&s->c, T, G, sig, &kt, s->cp);
+    double e = 0.0;
+    for (int a = 0; a < 9; a++) e += sig[a] * G[a];
+    out[5 * N + i] = e;
+    const double ox = G[7] - G[5], oy = G[2] - G[6], oz = G[3] - G[1];
+    out[6 * N + i] = ox * ox + oy * oy + oz * oz;
+  }
+  ora_destroy(s);
+  return ORA_OK;
+}
+
 /* Number of points whose stencil in some direction reaches across a PE face (N_B, Eq. NB),
  * counted by walking each point's stencil. */
 int64_t ora_count_at_points(const ora_config* cfg) {

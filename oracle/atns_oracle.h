@@ -76,6 +76,8 @@ int64_t ora_count_at_points(const ora_config* cfg);
 int ora_forcing_field(const ora_config* cfg, const double* fhat_step, double* out /*[3][N]*/);
 uint64_t ora_splitmix64(uint64_t seed, uint64_t counter);
 int ora_get_flux(const ora_sim* s, double* out);   /* [3][5][N] from the last RHS evaluation */
+/* [7][N]: u, v, w, p, du/dx, sigma_ij du_i/dx_j, |curl u|^2 with synchronous periodic derivatives */
+int ora_diag_fields(const ora_config* cfg, const double* q, double* out);
 
 #ifdef __cplusplus
 }

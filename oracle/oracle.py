@@ -110,6 +110,7 @@ def _load():
         lib.ora_count_at_points.argtypes = [C.POINTER(_Cfg)]
         lib.ora_count_at_points.restype = i64
         lib.ora_forcing_field.argtypes = [C.POINTER(_Cfg), dp, dp]
+        lib.ora_diag_fields.argtypes = [C.POINTER(_Cfg), dp, dp]
         lib.ora_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         lib.ora_splitmix64.restype = C.c_uint64
         _lib = lib
@@ -243,6 +244,17 @@ class Oracle:
         fh = np.ascontiguousarray(fhat_step, dtype=np.float64)
         out = np.zeros((3,) + cfg.shape)
         _load().ora_forcing_field(C.byref(c), _dp(fh), _dp(out))
+        return out
+
+    @staticmethod
+    def diag_fields(cfg: OracleConfig, q: np.ndarray) -> np.ndarray:
+        """[7][...]: u, v, w, p, du/dx, sigma_ij du_i/dx_j, |curl u|^2 (synchronous derivatives)."""
+        c = cfg.to_c()
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        out = np.zeros((7,) + cfg.shape)
+        rc = _load().ora_diag_fields(C.byref(c), _dp(q), _dp(out))
+        if rc:
+            raise OracleError("diag_fields", rc)
         return out
 
     @staticmethod
