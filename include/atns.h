@@ -237,6 +237,54 @@ ATNS_API int at_destroy(at_sim* sim);
 ATNS_API int at_field_stats_noalloc(const at_config* cfg, const void* dev_q, at_stats_t* dev_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Turbulence diagnostics of one field (Sec. 4.1): the statistics the paper compares between the
+ * synchronous and asynchronous runs, computed on the device in FP64 for a field in either
+ * precision.  With u_k the discrete Fourier coefficient of u (the forward sum over the grid of
+ * u(x) exp(-i k.x), divided by the number of points N) and the shells kappa = round(|k|) of the
+ * integer wavevectors (index j of an axis of n points is wavenumber j for j <= n/2, else j - n):
+ *   E(kappa)   = sum over the shell of (|u_k|^2 + |v_k|^2 + |w_k|^2) / 2   (Sec. 4.1.2, Eq. ener;
+ *                the shells add up to <u.u> / 2)
+ *   E_p(kappa) = sum over the shell of |p_k|^2, p = rho R T                 (Eq. pres; E_p(0) = <p>^2)
+ *   S = <g^3> / <g^2>^(3/2), F = <g^4> / <g^2>^2 of g = du/dx               (Sec. 4.1.3; 0 if <g^2> = 0)
+ *   counts of x = eps / <eps> and of x = Omega / <Omega> (eps = sigma_ij du_i/dx_j, Omega =
+ *   |curl u|^2; Sec. 4.1.3, Fig. enst_pdf) in nbins equal bins of [0, x_max), bin =
+ *   floor(x (nbins / x_max)) in FP64, values below 0 in bin 0 and values >= x_max in bin nbins; a
+ *   PDF whose mean is not positive and finite has all counts 0.
+ * Derivatives are the synchronous central ones of cfg->order on the periodic grid (those of
+ * at_stats).  Spectra come from in-place FFTs of the four real fields along x, y and z; the shell
+ * sums and all reductions run in a fixed order (results do not change from call to call), the
+ * counts are exact integers.
+ * ------------------------------------------------------------------------------------------- */
+#define AT_DIAG_MAX_SHELLS 4096
+#define AT_DIAG_MAX_BINS 4096
+#define AT_DIAG_N_SCALARS 8
+typedef struct at_diag_params {
+  int32_t nshell;      /* shells 0 .. nshell-1 reported (1 .. AT_DIAG_MAX_SHELLS); higher ones are    */
+                       /* left out of E and E_p                                                        */
+  int32_t nbins;       /* bins of each PDF (1 .. AT_DIAG_MAX_BINS), plus one for x >= x_max           */
+  double eps_max;      /* x_max of eps / <eps> (> 0)                                                   */
+  double ens_max;      /* x_max of Omega / <Omega> (> 0)                                               */
+} at_diag_params;
+
+/* Bytes of device workspace at_field_diagnostics needs (0 if cfg or prm is invalid): the half
+ * spectra of u, v, w, p (4 nz ny px complex doubles, px = nx/2 + 1 rounded up to a multiple of 8),
+ * plus reduction partials. */
+ATNS_API size_t at_diag_workspace_bytes(const at_config* cfg, const at_diag_params* prm);
+
+/* Diagnostics of the device field dev_q ([5][nz][ny][nx] conserved variables in cfg->precision,
+ * read only), enqueued on hip_stream (NULL = default) without synchronising.
+ *   cfg:     used: n (each a power of two from 8 to 1024), order, precision, gamma, gas_r, mu_ref,
+ *            t_ref, mu_exp; validated as at_create does.
+ *   dev_ws:  device workspace of at least at_diag_workspace_bytes bytes, 256-byte aligned, owned by
+ *            the caller; overwritten.
+ *   dev_out: device doubles, 2 nshell + AT_DIAG_N_SCALARS + 2 (nbins + 1) of them: E[nshell],
+ *            E_p[nshell], then S, F, <g^2>, <g^3>, <g^4>, <eps>, <Omega>, <p>, then the counts of
+ *            eps / <eps> [nbins + 1] and of Omega / <Omega> [nbins + 1] (exact integers).
+ * Errors: AT_E_INVAL (config, grid sizes, parameters, NULL pointers), AT_E_WORKSPACE, AT_E_HIP. */
+ATNS_API int at_field_diagnostics(const at_config* cfg, const void* dev_q, void* dev_ws, size_t ws_bytes,
+                                  const at_diag_params* prm, double* dev_out, void* hip_stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Batched runs.  Many independent runs (any grid, PE grid, delays, forcing, time step and
  * viscosity; one precision) advanced together: one launch per kernel per RK stage covers the
  * workgroups of every member, reading each member's arguments from a device run table through a

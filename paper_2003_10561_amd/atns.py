@@ -27,7 +27,8 @@ EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "a
             "at_batch_create", "at_batch_add", "at_batch_remove", "at_batch_size", "at_batch_step",
             "at_batch_set_tuning", "at_batch_get_tuning", "at_batch_set_stage_tuning",
             "at_batch_get_stage_tuning", "at_batch_autotune", "at_batch_set_graph",
-            "at_batch_graph_stats", "at_batch_destroy", "at_serve", "at_field_stats_noalloc"]
+            "at_batch_graph_stats", "at_batch_destroy", "at_serve", "at_field_stats_noalloc",
+            "at_diag_workspace_bytes", "at_field_diagnostics"]
 N_TILES = 7
 N_KERNELS = 8
 
@@ -70,6 +71,13 @@ class _Result(C.Structure):
     _fields_ = [("admit_s", C.c_double), ("done_s", C.c_double), ("stats", _Stats), ("status", C.c_int32),
                 ("reserved", C.c_int32)]
 
+
+class _DiagParams(C.Structure):
+    _fields_ = [("nshell", C.c_int32), ("nbins", C.c_int32), ("eps_max", C.c_double), ("ens_max", C.c_double)]
+
+
+DIAG_N_SCALARS = 8
+DIAG_SCALARS = ("S", "F", "g2", "g3", "g4", "eps_mean", "ens_mean", "p_mean")
 
 _lib = None
 
@@ -121,6 +129,9 @@ def load_library(path: str = LIB_PATH):
     lib.at_batch_destroy.argtypes = [vp]
     lib.at_serve.argtypes = [C.POINTER(_ServeConfig), C.POINTER(_Request), i32, vp, C.POINTER(_Result), dp]
     lib.at_field_stats_noalloc.argtypes = [C.POINTER(_Config), vp, vp, vp]
+    lib.at_diag_workspace_bytes.argtypes = [C.POINTER(_Config), C.POINTER(_DiagParams)]
+    lib.at_diag_workspace_bytes.restype = C.c_size_t
+    lib.at_field_diagnostics.argtypes = [C.POINTER(_Config), vp, vp, C.c_size_t, C.POINTER(_DiagParams), vp, vp]
     _lib = lib
     return lib
 
@@ -299,6 +310,11 @@ class Sim:
         _check("at_field_device", self.lib.at_field_device(self.h, C.byref(p)))
         return int(p.value)
 
+    def diagnostics(self, nshell: int, nbins: int, eps_max: float, ens_max: float, workspace=None) -> dict:
+        """at_field_diagnostics of the current state on the run's stream (see field_diagnostics)."""
+        return field_diagnostics(self.cfg, self.field_device_ptr(), nshell, nbins, eps_max, ens_max,
+                                 workspace=workspace, stream=self.stream)
+
 
 class Batch:
     """Batched runs (include/atns.h, at_batch_*): members advance together, one launch per kernel
@@ -424,3 +440,53 @@ def stats_record(raw: bytes) -> dict:
     """A statistics record (as written by field_stats_noalloc) as a dict."""
     s = _Stats.from_buffer_copy(raw)
     return _stats_dict(s)
+
+
+def diag_params(nshell: int, nbins: int, eps_max: float, ens_max: float) -> _DiagParams:
+    return _DiagParams(int(nshell), int(nbins), float(eps_max), float(ens_max))
+
+
+def diag_workspace_bytes(cfg: Config, nshell: int, nbins: int, eps_max: float, ens_max: float) -> int:
+    c, p = cfg.to_c(), diag_params(nshell, nbins, eps_max, ens_max)
+    return int(load_library().at_diag_workspace_bytes(C.byref(c), C.byref(p)))
+
+
+def field_diagnostics(cfg: Config, dev_q: int, nshell: int, nbins: int, eps_max: float, ens_max: float,
+                      workspace=None, stream=None, out=None, sync: bool = True):
+    """at_field_diagnostics of the device field at `dev_q` (cfg's precision, [5][nz][ny][nx]).
+
+    workspace: a torch uint8 device tensor of at least diag_workspace_bytes (allocated here if None);
+    out: a torch float64 device tensor for the raw output (allocated if None).  With sync=True the
+    result is returned as a dict of numpy arrays and floats (E, Ep, S, F, g2, g3, g4, eps_mean,
+    ens_mean, p_mean, eps_pdf, ens_pdf); with sync=False the raw device tensor is returned unread."""
+    import torch
+    lib = load_library()
+    c, p = cfg.to_c(), diag_params(nshell, nbins, eps_max, ens_max)
+    nbytes = int(lib.at_diag_workspace_bytes(C.byref(c), C.byref(p)))
+    if nbytes == 0:
+        raise AtError("at_diag_workspace_bytes", AT_E_INVAL, lib.at_last_error().decode())
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    nout = 2 * nshell + DIAG_N_SCALARS + 2 * (nbins + 1)
+    if out is None:
+        out = torch.empty(nout, dtype=torch.float64, device=workspace.device)
+    assert out.dtype == torch.float64 and out.numel() >= nout and out.is_contiguous()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check("at_field_diagnostics", lib.at_field_diagnostics(
+        C.byref(c), C.c_void_p(dev_q), C.c_void_p(workspace.data_ptr()), workspace.numel(), C.byref(p),
+        C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+    if not sync:
+        return out
+    st.synchronize()
+    return diag_dict(out.cpu().numpy(), nshell, nbins)
+
+
+def diag_dict(raw: np.ndarray, nshell: int, nbins: int) -> dict:
+    """The output array of at_field_diagnostics as a dict."""
+    d = {"E": raw[:nshell].copy(), "Ep": raw[nshell:2 * nshell].copy()}
+    sc = raw[2 * nshell:2 * nshell + DIAG_N_SCALARS]
+    d.update({k: float(v) for k, v in zip(DIAG_SCALARS, sc)})
+    o = 2 * nshell + DIAG_N_SCALARS
+    d["eps_pdf"] = raw[o:o + nbins + 1].astype(np.int64)
+    d["ens_pdf"] = raw[o + nbins + 1:o + 2 * (nbins + 1)].astype(np.int64)
+    return d
