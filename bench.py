@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cfg2", action="store_true", help="skip the decaying 256^3 FP64 configuration")
     ap.add_argument("--no-order6", action="store_true", help="skip the sixth-order scheme")
+    ap.add_argument("--no-diag", action="store_true", help="skip the turbulence diagnostics of the final state")
     ap.add_argument("--cfg2-steps", type=int, default=100)
     ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
     ap.add_argument("--zchunk", type=int, default=None)
@@ -444,6 +445,49 @@ def decaying_cfg2(torch, atns, W, traffic, steps):
                         "statistics every step"}
 
 
+def diag_leg(torch, atns, sim, n, reps=3):
+    """Turbulence diagnostics (Sec. 4.1: E(kappa), E_p(kappa), S and F of du/dx, PDFs of eps/<eps> and
+    Omega/<Omega>) of the headline run's final FP32 state, timed with HIP events on the run's stream."""
+    nshell = int(math.isqrt(3 * (n // 2) ** 2)) + 2
+    nbins, emax, omax = 200, 20.0, 40.0
+    ws = torch.empty(atns.diag_workspace_bytes(sim.cfg, nshell, nbins, emax, omax), dtype=torch.uint8, device="cuda")
+    raw = torch.empty(2 * nshell + atns.DIAG_N_SCALARS + 2 * (nbins + 1), dtype=torch.float64, device="cuda")
+    st = sim.stream
+    qp = sim.field_device_ptr()
+
+    def call():
+        atns.field_diagnostics(sim.cfg, qp, nshell, nbins, emax, omax, workspace=ws, stream=st, out=raw, sync=False)
+
+    call()
+    st.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        call()
+    e1.record(st)
+    st.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    d = atns.diag_dict(raw.cpu().numpy(), nshell, nbins)
+    del ws, raw
+    # algorithmic bytes per point: the field read by the moment, histogram and x-transform passes
+    # (3 x 5 FP32 words), and the half spectra of u, v, w, p (4 x 16 B x (n/2 + 1) / n) written by
+    # the x pass, read and written by the y pass and read by the z pass
+    bpp = 3 * 5 * 4 + 4 * 16 * (n // 2 + 1) / n * 4
+    gbs = bpp * n ** 3 / (ms * 1e-3) / 1e9
+    E = d["E"]
+    return {"ms_per_call": ms, "calls": reps, "points": n ** 3, "nshell": nshell, "nbins": nbins,
+            "roofline": {"bound": "hbm", "kernel": "all diagnostics launches", "achieved": gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_point": bpp, "traffic": None},
+            "S": d["S"], "F": d["F"], "eps_mean": d["eps_mean"], "ens_mean": d["ens_mean"],
+            "E_total": float(E.sum()), "E_peak_shell": int(np.argmax(E[1:]) + 1),
+            "Ep_total_fluct": float(d["Ep"][1:].sum()),
+            "eps_pdf_tail_gt10": int(d["eps_pdf"][nbins * 10 // int(emax):].sum()),
+            "ens_pdf_tail_gt10": int(d["ens_pdf"][nbins * 10 // int(omax):].sum()),
+            "workload": f"{n}^3 FP32 state after the timed RK3 steps; {nshell} shells, {nbins} PDF bins "
+                        f"on [0, {emax:g}) and [0, {omax:g}), FP64 arithmetic"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -480,6 +524,10 @@ def main():
     ms32 = time_window(torch, sim, K, warmup=Wm)
     ms32_ev, kt32 = kernel_window(torch, sim, K)
     st32 = sim.stats()
+    diag = None
+    if not args.no_diag:
+        diag = diag_leg(torch, atns, sim, n)
+        log(f"diagnostics: {diag}")
     f32 = sim.get_field() if not args.no_fp64 else None
     if not args.no_ab2:
         sim.ab2_step(AB2_WARM)
@@ -505,6 +553,8 @@ def main():
                              "launches": {k: v[1] for k, v in kt32.items()}},
            "hbm_gbs_algorithmic": traffic.bytes_per_point_step((n,) * 3, (pe,) * 3, pd, 4) * value / 1e9,
            "stats_after": {k: st32[k] for k in ("K", "eps", "enstrophy", "Mt", "nonfinite")}}
+    if diag is not None:
+        out["diagnostics"] = diag
     if not args.no_ab2:
         # the paper's own integrator (Sec. 2.2, Eq. time_ab): one RHS per step; not the headline
         pd_ab2 = traffic.delayed_fraction(sched[Wm + 2 * K + AB2_WARM:Wm + 3 * K + AB2_WARM])

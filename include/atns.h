@@ -268,7 +268,7 @@ typedef struct at_diag_params {
 
 /* Bytes of device workspace at_field_diagnostics needs (0 if cfg or prm is invalid): the half
  * spectra of u, v, w, p (4 nz ny px complex doubles, px = nx/2 + 1 rounded up to a multiple of 8),
- * plus reduction partials. */
+ * eps and Omega of every point (2 N doubles), plus reduction partials: about 50 N bytes at 512^3. */
 ATNS_API size_t at_diag_workspace_bytes(const at_config* cfg, const at_diag_params* prm);
 
 /* Diagnostics of the device field dev_q ([5][nz][ny][nx] conserved variables in cfg->precision,

@@ -4,11 +4,12 @@
 // enst_pdf) as integer counts.  Everything in FP64 whatever the field precision.
 //
 // Passes (one stream, no host synchronisation):
-//   1. k_diag_pts<moments>: synchronous central gradients of the run's order; per-workgroup FP64
-//      sums of g^2, g^3, g^4 (g = du/dx), eps = sigma_ij du_i/dx_j, Omega = |curl u|^2 and p,
-//      reduced in a fixed order (k_mom_reduce, k_mom_final) into the means and S, F.
-//   2. k_diag_pts<histogram>: the same per-point values again, binned against the means; LDS
-//      histograms, flushed with 64-bit integer atomics (exact and order-free).
+//   1. k_diag_pts: synchronous central gradients of the run's order; per-workgroup FP64 sums of
+//      g^2, g^3, g^4 (g = du/dx), eps = sigma_ij du_i/dx_j, Omega = |curl u|^2 and p, reduced in a
+//      fixed order (k_mom_reduce, k_mom_final) into the means and S, F; eps and Omega of every
+//      point kept in the workspace.
+//   2. k_diag_hist: eps and Omega binned against the means; LDS histograms, flushed with 64-bit
+//      integer atomics (exact and order-free).
 //   3. k_fft_x: rows of the conservative field -> u, v, w, p in FP64 -> (u + i v) and (w + i p)
 //      transformed along x in LDS -> separated into the half spectra (kx = 0 .. nx/2) of the four
 //      real fields.
@@ -44,6 +45,7 @@ constexpr int kMaxBins = AT_DIAG_MAX_BINS;
 // for the rest.
 struct Axis {
   int n;
+  int lg;              // log2 n
   int nst;
   int lr[kMaxStages];  // log2 of each stage's radix, in the order the stages run
   int tws;             // twiddle table stride: table length / n
@@ -54,6 +56,7 @@ Axis make_axis(int n, int ntw) {
   a.n = n;
   int m = 0;
   while ((1 << m) < n) ++m;
+  a.lg = m;
   for (int i = 0; i < m / 3; ++i) a.lr[a.nst++] = 3;
   if (m % 3) a.lr[a.nst++] = m % 3;
   a.tws = ntw / n;
@@ -73,11 +76,11 @@ __device__ __forceinline__ int pos_of(const Axis& a, int f) {
   return p;
 }
 __device__ __forceinline__ int freq_of(const Axis& a, int p) {
-  int k = 0, sh = 0, L = a.n;
+  int k = 0, sh = 0, lgL = a.lg;
   for (int i = 0; i < a.nst; ++i) {
-    L >>= a.lr[i];
-    k += (p / L) << sh;
-    p &= L - 1;
+    lgL -= a.lr[i];
+    k += (p >> lgL) << sh;
+    p &= (1 << lgL) - 1;
     sh += a.lr[i];
   }
   return k;
@@ -260,64 +263,73 @@ __device__ __forceinline__ int pdf_bin(double x, double scale, int nbins) {
   return (int)b;
 }
 
-// Point pass over 64 x 4 columns and kPtsZC planes per workgroup.  HIST = false: partial sums
-// [blk][kMom]; HIST = true: counts of eps / <eps> and Omega / <Omega> (means from sums).
-template <typename T, int M, bool HIST>
+// Point pass over 64 x 4 columns and kPtsZC planes per workgroup: partial sums [blk][kMom] of
+// g^2, g^3, g^4, eps, Omega and p, and (eps, Omega) of every point for the histogram pass.
+template <typename T, int M>
 __global__ __launch_bounds__(256) void k_diag_pts(const T* __restrict__ q, int nx, int ny, int nz, Phys ph,
-                                                  double* __restrict__ part, const double* __restrict__ sums,
-                                                  unsigned long long* __restrict__ hist, int nbins, double scale_e,
-                                                  double scale_o) {
-  extern __shared__ unsigned int hs[];  // HIST: [2][nbins + 1]
+                                                  double* __restrict__ part, double2* __restrict__ eo) {
   const int x = blockIdx.x * kPtsBX + threadIdx.x;
   const int y = blockIdx.y * kPtsBY + threadIdx.y;
   const int z0 = blockIdx.z * kPtsZC, z1 = min(z0 + kPtsZC, nz);
   const int tid = threadIdx.y * kPtsBX + threadIdx.x;
   const int64_t N = (int64_t)nx * ny * nz;
-  const bool valid = x < nx && y < ny;
-  if constexpr (HIST) {
-    const double inv_n = 1.0 / (double)N;
-    const double me = sums[3] * inv_n, mo = sums[4] * inv_n;
-    const bool do_e = me > 0.0 && isfinite(me), do_o = mo > 0.0 && isfinite(mo);
-    for (int b = tid; b < 2 * (nbins + 1); b += kThreads) hs[b] = 0u;
-    __syncthreads();
-    if (valid && (do_e || do_o)) {
-      for (int z = z0; z < z1; ++z) {
-        double g, e, o, p;
-        point_values<T, M>(q, nx, ny, nz, N, x, y, z, ph, g, e, o, p);
-        if (do_e) atomicAdd(&hs[pdf_bin(e / me, scale_e, nbins)], 1u);
-        if (do_o) atomicAdd(&hs[nbins + 1 + pdf_bin(o / mo, scale_o, nbins)], 1u);
-      }
-    }
-    __syncthreads();
-    for (int b = tid; b < 2 * (nbins + 1); b += kThreads)
-      if (hs[b]) atomicAdd(&hist[b], (unsigned long long)hs[b]);
-  } else {
-    double s[kMom] = {0, 0, 0, 0, 0, 0};
-    if (valid) {
-      for (int z = z0; z < z1; ++z) {
-        double g, e, o, p;
-        point_values<T, M>(q, nx, ny, nz, N, x, y, z, ph, g, e, o, p);
-        const double g2 = g * g;
-        s[0] += g2;
-        s[1] += g2 * g;
-        s[2] += g2 * g2;
-        s[3] += e;
-        s[4] += o;
-        s[5] += p;
-      }
-    }
-    __shared__ double red[kPtsBY][kMom];
-#pragma unroll
-    for (int c = 0; c < kMom; ++c) {
-      const double v = wsum(s[c]);
-      if (threadIdx.x == 0) red[threadIdx.y][c] = v;
-    }
-    __syncthreads();
-    if (tid < kMom) {
-      const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-      part[blk * kMom + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  double s[kMom] = {0, 0, 0, 0, 0, 0};
+  if (x < nx && y < ny) {
+    for (int z = z0; z < z1; ++z) {
+      double g, e, o, p;
+      point_values<T, M>(q, nx, ny, nz, N, x, y, z, ph, g, e, o, p);
+      eo[((int64_t)z * ny + y) * nx + x] = make_double2(e, o);
+      const double g2 = g * g;
+      s[0] += g2;
+      s[1] += g2 * g;
+      s[2] += g2 * g2;
+      s[3] += e;
+      s[4] += o;
+      s[5] += p;
     }
   }
+  __shared__ double red[kPtsBY][kMom];
+#pragma unroll
+  for (int c = 0; c < kMom; ++c) {
+    const double v = wsum(s[c]);
+    if (threadIdx.x == 0) red[threadIdx.y][c] = v;
+  }
+  __syncthreads();
+  if (tid < kMom) {
+    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    part[blk * kMom + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  }
+}
+
+constexpr int kHistPts = 16;  // points per thread of the histogram pass
+
+// Counts of eps / <eps> and Omega / <Omega> (means from the reduced sums) in LDS, flushed with
+// 64-bit integer atomics.
+__global__ __launch_bounds__(256) void k_diag_hist(const double2* __restrict__ eo, int64_t N,
+                                                   const double* __restrict__ sums,
+                                                   unsigned long long* __restrict__ hist, int nbins, double scale_e,
+                                                   double scale_o) {
+  extern __shared__ unsigned int hs[];  // [2][nbins + 1]
+  const double inv_n = 1.0 / (double)N;
+  const double me = sums[3] * inv_n, mo = sums[4] * inv_n;
+  const bool do_e = me > 0.0 && isfinite(me), do_o = mo > 0.0 && isfinite(mo);
+  for (int b = threadIdx.x; b < 2 * (nbins + 1); b += kThreads) hs[b] = 0u;
+  __syncthreads();
+  if (do_e || do_o) {
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads * kHistPts;
+#pragma unroll 4
+    for (int c = 0; c < kHistPts; ++c) {
+      const int64_t i = i0 + c * kThreads + threadIdx.x;
+      if (i < N) {
+        const double2 v = eo[i];
+        if (do_e) atomicAdd(&hs[pdf_bin(v.x / me, scale_e, nbins)], 1u);
+        if (do_o) atomicAdd(&hs[nbins + 1 + pdf_bin(v.y / mo, scale_o, nbins)], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < 2 * (nbins + 1); b += kThreads)
+    if (hs[b]) atomicAdd(&hist[b], (unsigned long long)hs[b]);
 }
 
 __device__ __forceinline__ double tree(double* red, double v) {
@@ -433,30 +445,35 @@ __global__ __launch_bounds__(256) void k_fft_y(double2* __restrict__ S, int nx, 
   }
 }
 
-__device__ __forceinline__ int64_t isqrt_floor(int64_t v) {
-  int64_t s = (int64_t)sqrt((double)v);
+// floor(sqrt(v)) of an integer 0 <= v < 2^24 (exact in FP32; corrected in integers).
+__device__ __forceinline__ int isqrt_floor(int v) {
+  int s = (int)sqrtf((float)v);
   while (s * s > v) --s;
   while ((s + 1) * (s + 1) <= v) ++s;
   return s;
 }
 // round(sqrt(k2)) of an integer k2 >= 0: no integer lies on a tie.
-__device__ __forceinline__ int shell_of(int64_t k2) {
-  const int64_t s = isqrt_floor(k2);
-  return (int)(k2 > s * s + s ? s + 1 : s);
+__device__ __forceinline__ int shell_of(int k2) {
+  const int s = isqrt_floor(k2);
+  return k2 > s * s + s ? s + 1 : s;
 }
 
+constexpr int kMaxPerThread = kLdsFft / (int)sizeof(double2) / kThreads;  // points per thread in the z pass
+
 // Transform along z of the columns kx0 .. kx0 + bx - 1 of one (field, y-position) row, then the
-// workgroup's shell sums: shell s >= 1 holds the k with s^2 - s < |k|^2 <= s^2 + s (shell 0 is k = 0), a contiguous run
-// of |kz| on every column, so one thread sums shell s over the columns (kx ascending) and both
-// halves of kz (kz >= 0, then kz < 0, |kz| ascending) with no atomics.  Columns 0 < kx < nx/2
-// count twice (their mirror images -k carry the same |F|^2).  part[wg][j] is shell lo + j, hdr
-// [wg] = (lo, count); velocity fields carry the factor 1/2 of the energy.
+// workgroup's shell sums.  |S|^2 of every point (times 2 on the columns 0 < kx < nx/2, whose mirror
+// images -k carry the same |F|^2) is first laid out per column in natural frequency order over the
+// transform's buffer.  Shell s >= 1 holds the k with s^2 - s < |k|^2 <= s^2 + s (shell 0 is k = 0):
+// on every column a contiguous run of |kz|, so one thread sums shell s over the columns (kx
+// ascending) and both halves of kz (kz >= 0, then kz < 0, |kz| ascending) with no atomics.
+// part[wg][j] is shell lo + j, hdr[wg] = (lo, count); velocity fields carry the factor 1/2 of the
+// energy.  |k|^2 <= 3 (n/2)^2 < 2^24 for n <= 1024.
 __global__ __launch_bounds__(256) void k_fft_z_shell(const double2* __restrict__ S, int nx, int ny, int nz, int px,
                                                      int bx, Axis ay, Axis az, const double2* __restrict__ tw,
                                                      int64_t fstride, int nshell, int spanmax,
                                                      double* __restrict__ part, int* __restrict__ hdr,
                                                      double inv_n2) {
-  extern __shared__ double2 lds[];  // [nz][bx]
+  extern __shared__ double2 lds[];  // [nz][bx]; then [bx][nz + 1] doubles
   const int kx0 = blockIdx.x * bx, py = blockIdx.y, f = blockIdx.z;
   const int nv = min(bx, nx / 2 + 1 - kx0);
   const double2* base = S + f * fstride + (int64_t)py * px + kx0;
@@ -467,8 +484,29 @@ __global__ __launch_bounds__(256) void k_fft_z_shell(const double2* __restrict__
   }
   __syncthreads();
   fft_lines(lds, az, bx, 1, bx, tw, true);
-  const int64_t ky = signed_k(freq_of(ay, py), ny);
-  const int64_t kxa = kx0, kxb = kx0 + nv - 1, kzh = nz / 2;
+  const int nzp = nz + 1;
+  double ev[kMaxPerThread];
+  int ei[kMaxPerThread];
+#pragma unroll
+  for (int c = 0; c < kMaxPerThread; ++c) {
+    const int t = threadIdx.x + c * kThreads;
+    ei[c] = -1;
+    if (t < nz * bx) {
+      const int p = t / bx, l = t - p * bx;
+      const double2 v = lds[t];
+      const int kx = kx0 + l;
+      ev[c] = (kx == 0 || kx == nx / 2 ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
+      ei[c] = l * nzp + freq_of(az, p);
+    }
+  }
+  __syncthreads();
+  double* en = (double*)lds;
+#pragma unroll
+  for (int c = 0; c < kMaxPerThread; ++c)
+    if (ei[c] >= 0) en[ei[c]] = ev[c];
+  __syncthreads();
+  const int ky = signed_k(freq_of(ay, py), ny);
+  const int kxa = kx0, kxb = kx0 + nv - 1, kzh = nz / 2;
   const int s_lo = shell_of(kxa * kxa + ky * ky);
   const int s_hi = min(shell_of(kxb * kxb + ky * ky + kzh * kzh), nshell - 1);
   const int span = max(0, s_hi - s_lo + 1);
@@ -479,24 +517,19 @@ __global__ __launch_bounds__(256) void k_fft_z_shell(const double2* __restrict__
   }
   const double scale = (f < 3 ? 0.5 : 1.0) * inv_n2;
   for (int j = threadIdx.x; j < span; j += kThreads) {
-    const int64_t s = s_lo + j;
-    const int64_t lo2 = s == 0 ? 0 : s * s - s + 1, hi2 = s * s + s;
+    const int s = s_lo + j;
+    const int lo2 = s == 0 ? 0 : s * s - s + 1, hi2 = s * s + s;
     double tot = 0.0;
     for (int l = 0; l < nv; ++l) {
-      const int64_t kx = kx0 + l, r = kx * kx + ky * ky;
-      if (hi2 - r < 0) continue;
-      int64_t a = lo2 - r <= 0 ? 0 : isqrt_floor(lo2 - r - 1) + 1;  // ceil(sqrt(lo2 - r))
-      const int64_t b = min(isqrt_floor(hi2 - r), kzh);
+      const int kx = kx0 + l, r = kx * kx + ky * ky;
+      if (hi2 < r) continue;
+      const int a = lo2 <= r ? 0 : isqrt_floor(lo2 - r - 1) + 1;  // ceil(sqrt(lo2 - r))
+      const int b = min(isqrt_floor(hi2 - r), kzh);
+      const double* row = en + l * nzp;
       double acc = 0.0;
-      for (int64_t kz = a; kz <= b; ++kz) {
-        const double2 v = lds[pos_of(az, (int)kz) * bx + l];
-        acc += v.x * v.x + v.y * v.y;
-      }
-      for (int64_t kz = max(a, (int64_t)1); kz <= min(b, kzh - 1); ++kz) {
-        const double2 v = lds[pos_of(az, (int)(nz - kz)) * bx + l];
-        acc += v.x * v.x + v.y * v.y;
-      }
-      tot += (kx == 0 || kx == nx / 2) ? acc : 2.0 * acc;
+      for (int kz = a; kz <= b; ++kz) acc += row[kz];
+      for (int kz = max(a, 1); kz <= min(b, kzh - 1); ++kz) acc += row[nz - kz];
+      tot += acc;
     }
     part[wg * spanmax + j] = tot * scale;
   }
@@ -542,7 +575,7 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 struct Plan {
   int nx, ny, nz, px, bxy, bxz, rows, ntw, nbxy, nbxz;
   int64_t nblk_pts, nwgz, spanmax;
-  size_t off_S, off_tw, off_part, off_mid, off_sums, off_hist, off_spart, off_hdr, off_smid, total;
+  size_t off_S, off_eo, off_tw, off_part, off_mid, off_sums, off_hist, off_spart, off_hdr, off_smid, total;
   dim3 pts_grid;
 };
 
@@ -580,6 +613,7 @@ int plan_of(const at_config* cfg, const at_diag_params* prm, Plan* pl) {
     return at;
   };
   p.off_S = take((size_t)4 * p.nz * p.ny * p.px * sizeof(double2));
+  p.off_eo = take((size_t)p.nx * p.ny * p.nz * sizeof(double2));
   p.off_tw = take((size_t)p.ntw * sizeof(double2));
   p.off_part = take((size_t)p.nblk_pts * kMom * sizeof(double));
   p.off_mid = take((size_t)kRed * kMom * sizeof(double));
@@ -611,6 +645,7 @@ int run_diag(const at_config* cfg, const Plan& pl, const at_diag_params* prm, co
   double* spart = (double*)(ws + pl.off_spart);
   int* hdr = (int*)(ws + pl.off_hdr);
   double* smid = (double*)(ws + pl.off_smid);
+  double2* eo = (double2*)(ws + pl.off_eo);
   const int nshell = prm->nshell, nb = prm->nbins;
   const int64_t N = (int64_t)pl.nx * pl.ny * pl.nz;
   double* o_scal = out + 2 * nshell;
@@ -618,15 +653,14 @@ int run_diag(const at_config* cfg, const Plan& pl, const at_diag_params* prm, co
 
   hipLaunchKernelGGL(k_twiddle, dim3((pl.ntw + 255) / 256), dim3(256), 0, st, tw, pl.ntw);
   const dim3 pblk(kPtsBX, kPtsBY);
-  hipLaunchKernelGGL((k_diag_pts<T, M, false>), pl.pts_grid, pblk, 0, st, q, pl.nx, pl.ny, pl.nz, ph, part,
-                     (const double*)nullptr, (unsigned long long*)nullptr, nb, 0.0, 0.0);
+  hipLaunchKernelGGL((k_diag_pts<T, M>), pl.pts_grid, pblk, 0, st, q, pl.nx, pl.ny, pl.nz, ph, part, eo);
   hipLaunchKernelGGL(k_mom_reduce, dim3(kRed), dim3(kThreads), 0, st, (const double*)part, pl.nblk_pts, mid);
   hipLaunchKernelGGL(k_mom_final, dim3(1), dim3(kThreads), 0, st, (const double*)mid, (double)N, sums, o_scal);
   const int nh2 = 2 * (nb + 1);
   hipLaunchKernelGGL(k_zero_u64, dim3((nh2 + 255) / 256), dim3(256), 0, st, hist, nh2);
-  hipLaunchKernelGGL((k_diag_pts<T, M, true>), pl.pts_grid, pblk, (size_t)nh2 * sizeof(unsigned int), st, q, pl.nx,
-                     pl.ny, pl.nz, ph, (double*)nullptr, (const double*)sums, hist, nb, (double)nb / prm->eps_max,
-                     (double)nb / prm->ens_max);
+  hipLaunchKernelGGL(k_diag_hist, dim3((unsigned)((N + kThreads * kHistPts - 1) / (kThreads * kHistPts))), dim3(kThreads),
+                     (size_t)nh2 * sizeof(unsigned int), st, (const double2*)eo, N, (const double*)sums, hist, nb,
+                     (double)nb / prm->eps_max, (double)nb / prm->ens_max);
   hipLaunchKernelGGL(k_counts_out, dim3((nh2 + 255) / 256), dim3(256), 0, st, (const unsigned long long*)hist, nh2,
                      o_cnt);
 

@@ -218,3 +218,79 @@ def test_invalid_arguments():
     small = torch.empty(1024, dtype=torch.uint8, device="cuda")
     with pytest.raises(atns.AtError):
         atns.field_diagnostics(gc, q.data_ptr(), 10, 10, 1.0, 1.0, workspace=small)
+
+
+def _modes_on_device(n, precision, B=0.2, C=0.15, c=0.4, d=0.7, T0=1.1, a=0.05, b=0.03):
+    """u = sin x + c sin 2x + d sin y, v = B sin(3x + 4y), w = C cos(x + y + z), rho = 1,
+    T = T0 + a cos 6x + b cos(2y + 2z), built with torch on the device as [5][n][n][n]."""
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * (2 * np.pi / n)
+    X, Y, Z = x.view(1, 1, n), x.view(1, n, 1), x.view(n, 1, 1)
+    u = torch.sin(X) + c * torch.sin(2 * X) + d * torch.sin(Y)
+    v = B * torch.sin(3 * X + 4 * Y)
+    w = C * torch.cos(X + Y + Z)
+    T = T0 + a * torch.cos(6 * X) + b * torch.cos(2 * Y + 2 * Z)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    q = torch.empty((5, n, n, n), dtype=dt, device="cuda")
+    q[0] = 1.0
+    q[1] = u.expand(n, n, n)
+    q[2] = v.expand(n, n, n)
+    q[3] = w.expand(n, n, n)
+    cv = R / (GAMMA - 1.0)
+    q[4] = cv * T + 0.5 * (u * u + v * v + w * w)
+    return q
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_closed_forms(precision):
+    """512^3, the benchmark's grid, with closed-form answers: E(1) = (1 + d^2)/4, E(2) = (c^2 + C^2)/4,
+    E(5) = B^2/4 and nothing elsewhere; E_p(0) = (R T0)^2, E_p(6) = R^2 a^2/2, E_p(3) = R^2 b^2/2 (|(0,2,2)|
+    rounds to 3); S and F of a cos x + b cos 2x with the modified wavenumbers of the 4th-order
+    stencil.  FP64: 1e-12 relative on the listed shells, 1e-13 of the total on the others; FP32 (the
+    field rounded to FP32 first, u_f = 6e-8; du/dx multiplies it by about 1.5 / h): 1e-6 and 1e-10."""
+    n = 512
+    say(f"case full-size diagnostics closed forms {n}^3 {precision}")
+    B, C, c, d, T0, a, b = 0.2, 0.15, 0.4, 0.7, 1.1, 0.05, 0.03
+    q = _modes_on_device(n, precision, B, C, c, d, T0, a, b)
+    gc = atns.Config(n=(n,) * 3, p=(8,) * 3, dt=1e-4, mu_ref=1e-3, max_delay=3, precision=precision)
+    nshell = int(np.floor(np.sqrt(3) * n / 2)) + 2
+    dgn = atns.field_diagnostics(gc, q.data_ptr(), nshell, 100, 10.0, 10.0)
+    del q
+    torch.cuda.empty_cache()
+    E, Ep = dgn["E"], dgn["Ep"]
+    wE = {1: (1 + d * d) / 4, 2: (c * c + C * C) / 4, 5: B * B / 4}
+    wP = {0: (R * T0) ** 2, 6: R * R * a * a / 2, 3: R * R * b * b / 2}
+    tl, to = (1e-12, 1e-13) if precision == "fp64" else (1e-6, 1e-10)
+    for got, want in ((E, wE), (Ep, wP)):
+        tot = sum(want.values())
+        for s in range(nshell):
+            if s in want:
+                assert abs(got[s] - want[s]) <= tl * want[s] + to * tot, (s, got[s], want[s])
+            else:
+                assert abs(got[s]) <= to * tot, (s, got[s])
+    h = 2 * np.pi / n
+    k1 = (8 * np.sin(h) - np.sin(2 * h)) / (6 * h)
+    k2 = c * (8 * np.sin(2 * h) - np.sin(4 * h)) / (6 * h)
+    g2 = (k1 * k1 + k2 * k2) / 2
+    S = 3 * k1 * k1 * k2 / 4 / g2 ** 1.5
+    Fl = (3 * (k1 ** 4 + k2 ** 4) / 8 + 3 * k1 * k1 * k2 * k2 / 2) / g2 ** 2
+    ts = 1e-12 if precision == "fp64" else 1e-5
+    assert abs(dgn["S"] - S) <= ts and abs(dgn["F"] - Fl) <= ts * Fl and abs(dgn["g2"] - g2) <= ts * g2
+    assert dgn["eps_pdf"].sum() == n ** 3 and dgn["ens_pdf"].sum() == n ** 3
+    assert dgn["p_mean"] == pytest.approx(R * T0, rel=1e-12 if precision == "fp64" else 1e-6)
+    say(f"  S {dgn['S']:.12f} (closed form {S:.12f}), F {dgn['F']:.12f} ({Fl:.12f})")
+
+
+@pytest.mark.slow
+def test_256_fp64_against_oracle():
+    """256^3 FP64 (the decaying configuration's grid) against the oracle on the whole output."""
+    n = 256
+    say(f"case diagnostics {n}^3 fp64 against the oracle")
+    q = perturbed_field((n,) * 3, seed=41)
+    gc, oc = cfg_pair((n,) * 3, 4, "fp64", mu=2e-3)
+    nshell = int(np.floor(np.sqrt(3) * n / 2)) + 2
+    dq = device_field(q, "fp64")
+    got = atns.field_diagnostics(gc, dq.data_ptr(), nshell, 120, 12.0, 24.0)
+    del dq
+    ref = oracle_diagnostics(oc, q, nshell, 120, 12.0, 24.0)
+    check(got, ref, 120, 12.0, 24.0, f"{n}^3 fp64")
