@@ -137,15 +137,21 @@ ATNS_API int at_init_field(at_sim* sim, const double* q_host, int32_t n_levels);
 ATNS_API int at_set_delay_schedule(at_sim* sim, int32_t mode, int32_t L, int32_t c_r,
                                    uint64_t seed, const int8_t* table, int64_t n_steps);
 
-/* Forcing amplitudes for absolute steps 0 .. n_steps-1: host float64 [n_steps][40][3][2]
- * (re, im).  The 40 wavevectors are the half space (kz > 0, or kz = 0 and ky > 0, or
- * kz = ky = 0 and kx > 0) of the integer k with 0 < |k|^2 <= 6, ordered by kz, then ky, then kx
- * ascending; f(x) = sum_k 2 Re(fhat_k exp(i k.x)), held fixed within a step.  Errors: AT_E_INVAL
- * (forcing disabled in the config, bad sizes), AT_E_HIP. */
+/* Forcing of the stationary runs (Sec. 4.2: a large-scale force f added as rho f to the momentum
+ * and rho f.u to the energy equation), amplitudes for absolute steps 0 .. n_steps-1: host float64
+ * [n_steps][40][3][2] (re, im), copied before the call returns.  The 40 wavevectors are the half
+ * space (kz > 0, or kz = 0 and ky > 0, or kz = ky = 0 and kx > 0) of the integer k with
+ * 0 < |k|^2 <= 6, ordered by kz, then ky, then kx ascending; f(x) = sum_k 2 Re(fhat_k exp(i k.x)),
+ * held fixed within a step.  Errors: AT_E_INVAL (forcing disabled in the config, bad sizes),
+ * AT_E_HIP. */
 ATNS_API int at_set_forcing(at_sim* sim, const double* fhat_host, int64_t n_steps);
 
-/* RHS at the current state and step with that step's delays at stage time c = 0, without
- * publishing or changing the state.  dev_out: device [5][nz][ny][nx] in the config's precision.
+/* RHS of the compressible Navier-Stokes equations (Sec. 2, Eqs. cont, mome, ie, in total-energy
+ * flux form) at the current state and step: gradients and flux divergences by the central rows of
+ * cfg->order, replaced across every delayed PE face by the AT stencils (Sec. 2.1, Eq. at; Appendix
+ * B, the (1,4) or (1,6) rows) with that step's delays at stage time c = 0, plus the forcing
+ * source of at_set_forcing; the state is neither published nor changed.  dev_out: device
+ * [5][nz][ny][nx] in the config's precision, owned by the caller.
  * Errors: AT_E_STATE, AT_E_SCHEDULE, AT_E_HIP. */
 ATNS_API int at_rhs(at_sim* sim, void* dev_out);
 
