@@ -48,6 +48,7 @@ struct ora_sim {
   int64_t slab[3];       /* points in one published slab set of direction d */
   double* ring_pub[3];   /* [R][4][slab[d]] primitives published on faces normal to d */
   double* ring_flux[3];  /* [R][5][slab[d]] flux F_d published on faces normal to d    */
+  double* ring_q[3];     /* form 1: [R][5][slab[d]] conserved variables on faces normal to d */
   int64_t* slot_level;   /* [R] level held by each ring slot, -1 = empty */
   int8_t* sched;         /* [sched_steps][ntiles][6] */
   int64_t sched_steps;
@@ -89,6 +90,15 @@ static int check_config(const ora_config* c) {
   if (!(c->gamma > 1.0) || !(c->gas_r > 0.0) || !(c->prandtl > 0.0) || !(c->t_ref > 0.0))
     return ORA_E_INVAL;
   if (!(c->mu_ref >= 0.0) || !(c->dt > 0.0)) return ORA_E_INVAL;
+  if (c->form != 0 && c->form != 1) return ORA_E_INVAL;
+  if (c->visc != 0 && c->visc != 1) return ORA_E_INVAL;
+  if (c->visc == 1 && (c->form != 1 || !(c->suth_s > 0.0))) return ORA_E_INVAL;
+  if (c->form == 1) {
+    if (c->order != 4) return ORA_E_INVAL;
+    /* the one-sided stencils of the mixed derivatives take five points of one PE */
+    for (int d = 0; d < 3; d++)
+      if (c->n[d] / c->p[d] < 5) return ORA_E_INVAL;
+  }
   return ORA_OK;
 }
 
@@ -221,6 +231,7 @@ static double ring_read(ora_sim* s, int kind, int d, int comp, int64_t level, co
   const int64_t j = slab_index(s, d, r);
   if (j < 0) { set_err(s, ORA_E_STATE); return NAN; }
   if (kind == 0) return s->ring_pub[d][((int64_t)slot * NPUB + comp) * s->slab[d] + j];
+  if (kind == 2) return s->ring_q[d][((int64_t)slot * NQ + comp) * s->slab[d] + j];
   return s->ring_flux[d][((int64_t)slot * NQ + comp) * s->slab[d] + j];
 }
 
@@ -286,15 +297,34 @@ static void primitives(const ora_config* c, double cv, const double* q, int64_t 
                        double* pr) {
   const double rho = q[i];
   const double u = q[npts + i] / rho, v = q[2 * npts + i] / rho, w = q[3 * npts + i] / rho;
-  const double ke = 0.5 * (u * u + v * v + w * w);
-  (void)c;
   pr[0] = rho; pr[1] = u; pr[2] = v; pr[3] = w;
-  pr[4] = (q[4 * npts + i] / rho - ke) / cv;
+  if (c->form == 1) {
+    pr[4] = q[4 * npts + i] / rho / cv;               /* rho e = rho c_v T (Eq. ie) */
+  } else {
+    const double ke = 0.5 * (u * u + v * v + w * w);
+    pr[4] = (q[4 * npts + i] / rho - ke) / cv;        /* E = rho (c_v T + |u|^2 / 2) */
+  }
 }
+
+/* Viscosity laws: the power law, and Sutherland's law named in Sec. 2,
+ * mu = mu_ref (T / T_ref)^(3/2) (T_ref + S) / (T + S); with dmu/dT for the expanded viscous
+ * terms of the paper's form. */
+static double viscosity(const ora_config* c, double T, double* dmu) {
+  if (c->visc == 1) {
+    const double mu = c->mu_ref * pow(T / c->t_ref, 1.5) * (c->t_ref + c->suth_s) / (T + c->suth_s);
+    if (dmu) *dmu = mu * (1.5 / T - 1.0 / (T + c->suth_s));
+    return mu;
+  }
+  const double mu = c->mu_ref * pow(T / c->t_ref, c->mu_exp);
+  if (dmu) *dmu = c->mu_exp * mu / T;
+  return mu;
+}
+
+double ora_viscosity(const ora_config* cfg, double T, double* dmu_dT) { return viscosity(cfg, T, dmu_dT); }
 
 static void stress(const ora_config* c, double T, const double* G, double sig[9], double* kappa_t,
                    double cp) {
-  const double mu = c->mu_ref * pow(T / c->t_ref, c->mu_exp);
+  const double mu = viscosity(c, T, NULL);
   const double theta = G[0] + G[4] + G[8];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
@@ -400,6 +430,10 @@ int ora_create(const ora_config* cfg, ora_sim** out) {
     s->ring_pub[d] = (double*)malloc(sizeof(double) * s->R * NPUB * s->slab[d]);
     s->ring_flux[d] = (double*)malloc(sizeof(double) * s->R * NQ * s->slab[d]);
     ok = ok && s->ring_pub[d] && s->ring_flux[d];
+    if (cfg->form == 1) {
+      s->ring_q[d] = (double*)malloc(sizeof(double) * s->R * NQ * s->slab[d]);
+      ok = ok && s->ring_q[d];
+    }
   }
   if (!ok) { ora_destroy(s); return ORA_E_NOMEM; }
   for (int i = 0; i < s->R; i++) s->slot_level[i] = -1;
@@ -412,7 +446,7 @@ void ora_destroy(ora_sim* s) {
   if (!s) return;
   free(s->q); free(s->dq); free(s->prim); free(s->grad); free(s->flux); free(s->rhs);
   free(s->slot_level); free(s->sched); free(s->fhat);
-  for (int d = 0; d < 3; d++) { free(s->ring_pub[d]); free(s->ring_flux[d]); }
+  for (int d = 0; d < 3; d++) { free(s->ring_pub[d]); free(s->ring_flux[d]); free(s->ring_q[d]); }
   free(s);
 }
 
@@ -529,6 +563,202 @@ static void compute_divergence(ora_sim* s, const double* q, int stage, int sync,
       }
 }
 
+/* ------------------------------------------------------------------ the paper's own form (form 1)
+ * Sec. 2, Eqs. cont, mome, ie with (rho, rho u_i, rho e) as the variables (Sec. 3.1: the five
+ * variables each PE stores and sends):
+ *   d rho / dt    = - d(rho u_j)/dx_j
+ *   d rho u_i /dt = - d(rho u_i u_j)/dx_j - dp/dx_i + d sigma_ij / dx_j + rho f_i
+ *   d rho e / dt  = - d(rho e u_j)/dx_j - p du_j/dx_j + d(k dT/dx_j)/dx_j + sigma_ij S_ij
+ * with the viscous and conduction terms expanded as the paper computes them (Sec. 2.1):
+ *   d sigma_ij/dx_j = mu (d2 u_i/dx_j dx_j + 1/3 d/dx_i (du_k/dx_k))
+ *                     + mu'(T) dT/dx_j (du_i/dx_j + du_j/dx_i - 2/3 delta_ij du_k/dx_k),
+ *   d(k dT/dx_j)/dx_j = k d2T/dx_j dx_j + k'(T) (dT/dx_j)^2,  k = mu c_p / Pr.
+ * First derivatives: the (1,4) AT scheme; pure second derivatives: the (2,4) AT scheme (Appendix
+ * B); both take the value of the differentiated function at a ghost point across a delayed face
+ * from the delayed levels of the published conserved variables, f(q^{n-k-l}) extrapolated with the
+ * weights of Eq. at.  Mixed derivatives d2 f / dx_a dx_b: the AT first derivatives along b and
+ * along a at every point, then a derivative of each along the other direction that uses only the
+ * PE's own points (central where it fits, the standard one-sided fourth-order stencils at the two
+ * points next to a face), and the average of the two (Sec. 2.1, three steps). */
+
+/* Functions of the conserved variables that the form differentiates. */
+enum { FN_U = 0, FN_T = 3, FN_P = 4, FN_M = 5, FN_UU = 8, FN_EU = 17 };
+
+static double fn_of(const ora_sim* s, int fn, const double q[NQ]) {
+  const double rho = q[0];
+  if (fn < 3) return q[1 + fn] / rho;
+  if (fn == FN_T) return q[4] / rho / s->cv;
+  if (fn == FN_P) return rho * s->c.gas_r * (q[4] / rho / s->cv);
+  if (fn < FN_UU) return q[1 + (fn - FN_M)];
+  if (fn < FN_EU) { const int ij = fn - FN_UU; return q[1 + ij / 3] * q[1 + ij % 3] / rho; }
+  return q[4] * q[1 + (fn - FN_EU)] / rho;
+}
+
+static void publish_q(ora_sim* s, const double* q, int slot) {
+  const ora_config* c = &s->c;
+  const int64_t N = s->npts;
+  for (int d = 0; d < 3; d++) {
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < c->n[2]; z++)
+      for (int y = 0; y < c->n[1]; y++)
+        for (int x = 0; x < c->n[0]; x++) {
+          const int r[3] = {x, y, z};
+          const int64_t j = slab_index(s, d, r);
+          if (j < 0) continue;
+          const int64_t i = idx3(c, x, y, z);
+          for (int cc = 0; cc < NQ; cc++) s->ring_q[d][((int64_t)slot * NQ + cc) * s->slab[d] + j] = q[cc * N + i];
+        }
+  }
+}
+
+/* f at r = p + m e_d as the PE owning p sees it: inside or across a face with k = 0, f of the
+ * current state; across a face with delay k >= 1, sum_l w_l(k + c_s) f(q^{n-k-l}). */
+static double seen_fn(ora_sim* s, int fn, const double* q, int d, const int p[3], int m, int stage) {
+  const int e = s->e[d];
+  const int lr = p[d] % e + m;
+  int r[3] = {p[0], p[1], p[2]};
+  r[d] = wrap(p[d] + m, s->c.n[d]);
+  const int64_t ir = idx3(&s->c, r[0], r[1], r[2]);
+  double qv[NQ];
+  int k = 0;
+  if (lr < 0 || lr >= e) k = delay_of(s, tile_index(s, p), 2 * d + (lr < 0 ? 0 : 1));
+  if (k == 0) {
+    for (int cc = 0; cc < NQ; cc++) qv[cc] = q[cc * s->npts + ir];
+    return fn_of(s, fn, qv);
+  }
+  const double kap = (double)k + RK_C[stage];
+  double v = 0.0;
+  for (int l = 0; l < s->tl; l++) {
+    for (int cc = 0; cc < NQ; cc++) qv[cc] = ring_read(s, 2, d, cc, s->step - k - l, r);
+    v += at_weight(s, l, kap) * fn_of(s, fn, qv);
+  }
+  return v;
+}
+
+/* (1,4) AT first derivative and (2,4) AT second derivative of f along d at p (Appendix B: the
+ * delayed side's values replaced by their extrapolations, the stencils otherwise standard,
+ * (-f_{-2} + 16 f_{-1} - 30 f_0 + 16 f_{+1} - f_{+2}) / (12 h^2) for the second derivative). */
+static double d1_fn(ora_sim* s, int fn, const double* q, int d, const int p[3], int stage) {
+  double v[4];
+  int i = 0;
+  for (int m = -2; m <= 2; m++)
+    if (m != 0) v[i++] = seen_fn(s, fn, q, d, p, m, stage);
+  return d1_central(4, v, s->h[d]);
+}
+
+static double d2_fn(ora_sim* s, int fn, const double* q, int d, const int p[3], int stage) {
+  double v[5];
+  for (int m = -2; m <= 2; m++) v[m + 2] = seen_fn(s, fn, q, d, p, m, stage);
+  const double h = s->h[d];
+  return (-v[0] + 16.0 * v[1] - 30.0 * v[2] + 16.0 * v[3] - v[4]) / (12.0 * h * h);
+}
+
+/* Derivative at local index l of a line g[0 .. e-1] of one PE using only those points. */
+static double pe_d1(const double* g, int e, int l, double h) {
+  if (l >= 2 && l <= e - 3) return (g[l - 2] - 8.0 * g[l - 1] + 8.0 * g[l + 1] - g[l + 2]) / (12.0 * h);
+  if (l == 0) return (-25.0 * g[0] + 48.0 * g[1] - 36.0 * g[2] + 16.0 * g[3] - 3.0 * g[4]) / (12.0 * h);
+  if (l == 1) return (-3.0 * g[0] - 10.0 * g[1] + 18.0 * g[2] - 6.0 * g[3] + g[4]) / (12.0 * h);
+  if (l == e - 2)
+    return (3.0 * g[e - 1] + 10.0 * g[e - 2] - 18.0 * g[e - 3] + 6.0 * g[e - 4] - g[e - 5]) / (12.0 * h);
+  return (25.0 * g[e - 1] - 48.0 * g[e - 2] + 36.0 * g[e - 3] - 16.0 * g[e - 4] + 3.0 * g[e - 5]) / (12.0 * h);
+}
+
+int ora_pe_derivative(const double* g, int32_t e, double h, double* out) {
+  if (!g || !out || e < 5) return ORA_E_INVAL;
+  for (int l = 0; l < e; l++) out[l] = pe_d1(g, e, l, h);
+  return ORA_OK;
+}
+
+/* That derivative along a at p of the gradient component gi (s->grad), within p's PE. */
+static double pe_d1_grad(const ora_sim* s, int gi, int a, const int p[3]) {
+  const int e = s->e[a];
+  const int l = p[a] % e;
+  double line[e];
+  int r[3] = {p[0], p[1], p[2]};
+  for (int j = 0; j < e; j++) {
+    r[a] = p[a] - l + j;
+    line[j] = s->grad[(int64_t)gi * s->npts + idx3(&s->c, r[0], r[1], r[2])];
+  }
+  return pe_d1(line, e, l, s->h[a]);
+}
+
+/* d2 u_k / dx_a dx_b, a != b: the average of the two PE-local derivatives of the AT gradients. */
+static double mixed_u(const ora_sim* s, int k, int a, int b, const int p[3]) {
+  return 0.5 * (pe_d1_grad(s, 3 * k + b, a, p) + pe_d1_grad(s, 3 * k + a, b, p));
+}
+
+/* AT gradients of u, v, w, T (G_ij = du_i/dx_j, then dT/dx_j) from the conserved state. */
+static void gradients_paper(ora_sim* s, const double* q, int stage) {
+  const ora_config* c = &s->c;
+  const int64_t N = s->npts;
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < c->n[2]; z++)
+    for (int y = 0; y < c->n[1]; y++)
+      for (int x = 0; x < c->n[0]; x++) {
+        const int p[3] = {x, y, z};
+        const int64_t i = idx3(c, x, y, z);
+        for (int a = 0; a < 4; a++)
+          for (int d = 0; d < 3; d++) {
+            const int fn = a < 3 ? FN_U + a : FN_T;
+            s->grad[(int64_t)((a < 3) ? 3 * a + d : 9 + d) * N + i] = d1_fn(s, fn, q, d, p, stage);
+          }
+      }
+}
+
+static void rhs_paper(ora_sim* s, const double* q, int stage, double* out) {
+  const ora_config* c = &s->c;
+  const int64_t N = s->npts;
+  const double* fh = (c->forcing && s->fhat) ? s->fhat + s->step * NFORCE * 6 : NULL;
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < c->n[2]; z++)
+    for (int y = 0; y < c->n[1]; y++)
+      for (int x = 0; x < c->n[0]; x++) {
+        const int p[3] = {x, y, z};
+        const int64_t i = idx3(c, x, y, z);
+        double G[NG];
+        for (int g = 0; g < NG; g++) G[g] = s->grad[(int64_t)g * N + i];
+        const double rho = s->prim[i], T = s->prim[4 * N + i];
+        const double pres = rho * c->gas_r * T;
+        double dmu;
+        const double mu = viscosity(c, T, &dmu);
+        const double kt = mu * s->cp / c->prandtl, dkt = dmu * s->cp / c->prandtl;
+        const double th = G[0] + G[4] + G[8];
+        double f[3] = {0.0, 0.0, 0.0};
+        if (fh) force_at(c, s->kf, fh, p, f);
+        /* continuity */
+        double div = 0.0;
+        for (int j = 0; j < 3; j++) div += d1_fn(s, FN_M + j, q, j, p, stage);
+        out[i] = -div;
+        /* momentum */
+        for (int a = 0; a < 3; a++) {
+          double conv = 0.0, lap = 0.0;
+          for (int j = 0; j < 3; j++) {
+            conv += d1_fn(s, FN_UU + 3 * a + j, q, j, p, stage);
+            lap += d2_fn(s, FN_U + a, q, j, p, stage);
+          }
+          double gdiv = d2_fn(s, FN_U + a, q, a, p, stage);      /* d/dx_a (du_a/dx_a) */
+          for (int k = 0; k < 3; k++)
+            if (k != a) gdiv += mixed_u(s, k, a, k, p);          /* d/dx_a (du_k/dx_k) */
+          double visc = mu * (lap + gdiv / 3.0);
+          for (int j = 0; j < 3; j++)
+            visc += dmu * G[9 + j] * (G[3 * a + j] + G[3 * j + a] - (a == j ? 2.0 / 3.0 * th : 0.0));
+          out[(1 + a) * N + i] = -conv - d1_fn(s, FN_P, q, a, p, stage) + visc + rho * f[a];
+        }
+        /* internal energy */
+        double conv = 0.0, lapT = 0.0, grT = 0.0;
+        for (int j = 0; j < 3; j++) {
+          conv += d1_fn(s, FN_EU + j, q, j, p, stage);
+          lapT += d2_fn(s, FN_T, q, j, p, stage);
+          grT += G[9 + j] * G[9 + j];
+        }
+        double sig[9], kdummy;
+        stress(c, T, G, sig, &kdummy, s->cp);
+        double diss = 0.0;
+        for (int g = 0; g < 9; g++) diss += sig[g] * G[g];
+        out[4 * N + i] = -conv - pres * th + kt * lapT + dkt * grT + diss;
+      }
+}
+
 /* One RHS evaluation at step s->step, RK stage `stage`; publishes at stage 0 when asked. */
 static int eval_rhs(ora_sim* s, const double* q, int stage, int do_publish, double* out) {
   if (!s->sched || s->step >= s->sched_steps) return ORA_E_SCHEDULE;
@@ -536,6 +766,16 @@ static int eval_rhs(ora_sim* s, const double* q, int stage, int do_publish, doub
   s->err = 0;
   const int slot = (int)(s->step % s->R);
   compute_primitives(s, q);
+  if (s->c.form == 1) {
+    if (do_publish) {
+      s->slot_level[slot] = s->step;
+      publish_q(s, q, slot);
+    }
+    gradients_paper(s, q, stage);
+    if (s->err) return s->err;
+    rhs_paper(s, q, stage, out);
+    return s->err;
+  }
   if (do_publish) {
     s->slot_level[slot] = s->step;
     publish(s, 0, slot);
@@ -556,6 +796,11 @@ int ora_init_field(ora_sim* s, const double* q, int32_t nlev) {
   for (int lev = 0; lev < nlev - 1; lev++) {
     const double* ql = q + (int64_t)lev * NQ * N;
     const int slot = lev % s->R;
+    if (s->c.form == 1) {
+      s->slot_level[slot] = lev;
+      publish_q(s, ql, slot);
+      continue;
+    }
     compute_primitives(s, ql);
     s->slot_level[slot] = lev;
     publish(s, 0, slot);

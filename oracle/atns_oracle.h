@@ -40,6 +40,13 @@ typedef struct {
   int32_t order;         /* spatial order: 4 ((1,4) AT rows, t_l = 3 levels, M = 2 layers) or */
                          /* 6 ((1,6) AT rows, t_l = 4 levels, M = 3 layers)                   */
   double gamma, prandtl, gas_r, mu_ref, t_ref, mu_exp, dt;
+  int32_t form;          /* 0: total-energy flux form (conserved E, D1 o D1 viscous fluxes);      */
+                         /* 1: the paper's own discretisation (Sec. 2, Eqs. cont, mome, ie): the  */
+                         /*    fifth variable is rho e, viscous and conduction terms expanded with */
+                         /*    (2,4) AT second derivatives and 3-step mixed derivatives (order 4) */
+  int32_t visc;          /* viscosity law: 0 mu_ref (T/t_ref)^mu_exp; 1 Sutherland (form 1 only):  */
+                         /* mu_ref (T/t_ref)^(3/2) (t_ref + S) / (T + S)                           */
+  double suth_s;         /* Sutherland's constant S (same units as T)                              */
 } ora_config;
 
 /* stats vector layout (all doubles) */
@@ -78,6 +85,12 @@ uint64_t ora_splitmix64(uint64_t seed, uint64_t counter);
 int ora_get_flux(const ora_sim* s, double* out);   /* [3][5][N] from the last RHS evaluation */
 /* [7][N]: u, v, w, p, du/dx, sigma_ij du_i/dx_j, |curl u|^2 with synchronous periodic derivatives */
 int ora_diag_fields(const ora_config* cfg, const double* q, double* out);
+/* The derivative along a line of e points of one PE that uses only those points (the second
+ * step of the paper's mixed derivatives): central (1,4) where the stencil stays inside, the
+ * standard one-sided and biased fourth-order stencils at the two points next to each end. */
+int ora_pe_derivative(const double* g, int32_t e, double h, double* out);
+/* mu(T) and dmu/dT of the configured viscosity law. */
+double ora_viscosity(const ora_config* cfg, double T, double* dmu_dT);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,8 @@ class _Cfg(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("p", C.c_int32 * 3), ("max_delay", C.c_int32),
                 ("forcing", C.c_int32), ("order", C.c_int32), ("gamma", C.c_double), ("prandtl", C.c_double),
                 ("gas_r", C.c_double), ("mu_ref", C.c_double), ("t_ref", C.c_double),
-                ("mu_exp", C.c_double), ("dt", C.c_double)]
+                ("mu_exp", C.c_double), ("dt", C.c_double), ("form", C.c_int32), ("visc", C.c_int32),
+                ("suth_s", C.c_double)]
 
 
 @dataclass
@@ -51,6 +52,9 @@ class OracleConfig:
     t_ref: float = 1.0
     mu_exp: float = 0.76
     order: int = 4
+    form: int = 0          # 0 total-energy flux form, 1 the paper's own form (rho e, expanded terms)
+    visc: int = 0          # 0 power law, 1 Sutherland (form 1)
+    suth_s: float = 0.0    # Sutherland's constant
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -62,6 +66,9 @@ class OracleConfig:
         c.max_delay = int(self.max_delay)
         c.forcing = int(bool(self.forcing))
         c.order = int(self.order)
+        c.form = int(self.form)
+        c.visc = int(self.visc)
+        c.suth_s = float(self.suth_s)
         for k in ("gamma", "prandtl", "gas_r", "mu_ref", "t_ref", "mu_exp", "dt"):
             setattr(c, k, float(getattr(self, k)))
         return c
@@ -111,6 +118,9 @@ def _load():
         lib.ora_count_at_points.restype = i64
         lib.ora_forcing_field.argtypes = [C.POINTER(_Cfg), dp, dp]
         lib.ora_diag_fields.argtypes = [C.POINTER(_Cfg), dp, dp]
+        lib.ora_pe_derivative.argtypes = [dp, C.c_int32, C.c_double, dp]
+        lib.ora_viscosity.argtypes = [C.POINTER(_Cfg), C.c_double, dp]
+        lib.ora_viscosity.restype = C.c_double
         lib.ora_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         lib.ora_splitmix64.restype = C.c_uint64
         _lib = lib
@@ -256,6 +266,25 @@ class Oracle:
         if rc:
             raise OracleError("diag_fields", rc)
         return out
+
+    @staticmethod
+    def pe_derivative(g: np.ndarray, h: float) -> np.ndarray:
+        """Derivative along one PE's line of points using only those points (form 1 mixed
+        derivatives): central inside, one-sided / biased fourth order at the ends."""
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        out = np.zeros_like(g)
+        rc = _load().ora_pe_derivative(_dp(g), int(g.size), float(h), _dp(out))
+        if rc:
+            raise OracleError("pe_derivative", rc)
+        return out
+
+    @staticmethod
+    def viscosity(cfg: OracleConfig, T: float):
+        """(mu, dmu/dT) of the configured law."""
+        c = cfg.to_c()
+        d = C.c_double()
+        mu = _load().ora_viscosity(C.byref(c), float(T), C.byref(d))
+        return float(mu), float(d.value)
 
     @staticmethod
     def splitmix64(seed, counter) -> int:
