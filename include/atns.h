@@ -80,6 +80,17 @@ typedef struct at_config {
   double t_ref;        /* reference temperature of the viscosity law (1.0)                      */
   double mu_exp;       /* viscosity exponent (0.76)                                              */
   double dt;           /* fixed time step (Sec. 2.2: no CFL reduction inside the step loop)     */
+  int32_t form;        /* 0: total-energy flux form (the fifth variable is E = rho (c_v T +     */
+                       /*    |u|^2/2); viscous and heat fluxes differentiated twice by the first- */
+                       /*    derivative rows).  1: the paper's own discretisation (Sec. 2, Eqs.   */
+                       /*    cont, mome, ie): the fifth variable is rho e = rho c_v T, the viscous */
+                       /*    and conduction terms expanded into (2,4) AT second derivatives (App. */
+                       /*    B) and mixed derivatives taken in the three steps of Sec. 2.1, the    */
+                       /*    published layers hold the conserved variables (Sec. 3.1); order 4,    */
+                       /*    PE edges >= 5, unforced, single runs                                  */
+  int32_t visc_law;    /* 0: mu = mu_ref (T / t_ref)^mu_exp; 1 (form 1 only): Sutherland's law   */
+                       /*    named in Sec. 2, mu = mu_ref (T / t_ref)^(3/2) (t_ref + S) / (T + S)  */
+  double sutherland_s; /* Sutherland's constant S (same units as T; > 0 with visc_law 1)         */
 } at_config;
 
 typedef struct at_stats_s {
@@ -212,7 +223,7 @@ ATNS_API int at_get_stage_tuning(at_sim* sim, int32_t* tile_sync, int32_t* zchun
  * recorded on the handle's stream; at_kernel_timing synchronises the stream and returns, for kernel
  * `kernel` (0 .. AT_N_KERNELS-1, named by at_kernel_name), the summed event time in ms and the
  * number of launches since timing was enabled.  Errors: AT_E_INVAL, AT_E_HIP. */
-#define AT_N_KERNELS 8
+#define AT_N_KERNELS 11
 ATNS_API int at_set_kernel_timing(at_sim* sim, int32_t enable);
 ATNS_API int at_kernel_timing(at_sim* sim, int32_t kernel, double* total_ms, int64_t* launches);
 ATNS_API const char* at_kernel_name(int32_t kernel);

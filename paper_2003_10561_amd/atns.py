@@ -30,7 +30,7 @@ EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "a
             "at_batch_graph_stats", "at_batch_destroy", "at_serve", "at_field_stats_noalloc",
             "at_diag_workspace_bytes", "at_field_diagnostics"]
 N_TILES = 7
-N_KERNELS = 8
+N_KERNELS = 11
 
 
 class AtError(RuntimeError):
@@ -44,7 +44,7 @@ class _Config(C.Structure):
                 ("max_delay", C.c_int32), ("precision", C.c_int32), ("forcing", C.c_int32),
                 ("gamma", C.c_double), ("prandtl", C.c_double), ("gas_r", C.c_double),
                 ("mu_ref", C.c_double), ("t_ref", C.c_double), ("mu_exp", C.c_double),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("form", C.c_int32), ("visc_law", C.c_int32), ("sutherland_s", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -156,6 +156,9 @@ class Config:
     t_ref: float = 1.0
     mu_exp: float = 0.76
     order: int = 4
+    form: int = 0              # 0 total-energy flux form; 1 the paper's own form (rho e, expanded terms)
+    visc_law: int = 0          # 0 power law (mu_exp); 1 Sutherland (form 1)
+    sutherland_s: float = 0.0  # Sutherland's constant
 
     def to_c(self) -> _Config:
         c = _Config()
@@ -163,6 +166,9 @@ class Config:
             c.n[d] = int(self.n[d])
             c.p[d] = int(self.p[d])
         c.order = int(self.order)
+        c.form = int(self.form)
+        c.visc_law = int(self.visc_law)
+        c.sutherland_s = float(self.sutherland_s)
         c.max_delay = int(self.max_delay)
         c.precision = FP32 if self.precision == "fp32" else FP64
         c.forcing = int(bool(self.forcing))

@@ -41,6 +41,19 @@ int validate(const at_config* c) {
   for (int d = 0; d < 3; ++d)
     if (c->n[d] / c->p[d] < 2 * M) return fail(AT_E_INVAL, "PE edge n[d]/p[d] must be >= order");
   if (c->order == 6 && c->forcing) return fail(AT_E_INVAL, "forcing is not implemented for the sixth-order scheme");
+  if (c->form != 0 && c->form != 1) return fail(AT_E_INVAL, "form must be 0 or 1");
+  if (c->visc_law != 0 && c->visc_law != 1) return fail(AT_E_INVAL, "visc_law must be 0 or 1");
+  if (c->visc_law == 1 && (c->form != 1 || !(c->sutherland_s > 0.0) || !std::isfinite(c->sutherland_s)))
+    return fail(AT_E_INVAL, "Sutherland's law needs form 1 and a positive constant");
+  if (c->form == 1) {
+    if (c->order != 4) return fail(AT_E_INVAL, "the paper's form is built with the fourth-order rows");
+    if (c->forcing) return fail(AT_E_INVAL, "forcing is not implemented for the paper's form");
+    for (int d = 0; d < 3; ++d)
+      if (c->n[d] / c->p[d] < 5)
+        return fail(AT_E_INVAL, "the paper's form needs PE edges >= 5 (one-sided mixed-derivative stencils)");
+    if (12.0 * c->n[0] * c->n[1] * c->n[2] >= 4294967296.0)
+      return fail(AT_E_INVAL, "grid too large for one handle (element offsets must stay below 2^32)");
+  }
   if (c->max_delay < 0 || c->max_delay > kMaxDelay) return fail(AT_E_INVAL, "max_delay out of 0..8");
   if (c->precision != AT_FP64 && c->precision != AT_FP32) return fail(AT_E_INVAL, "bad precision");
   if (c->forcing != 0 && c->forcing != 1) return fail(AT_E_INVAL, "forcing must be 0 or 1");
@@ -61,6 +74,7 @@ int validate(const at_config* c) {
 
 Geom make_geom(const at_config* c) {
   Geom g{};
+  g.form = c->form;
   g.order = c->order;
   g.M = c->order / 2;
   g.tl = g.M + 1;
@@ -74,10 +88,13 @@ Geom make_geom(const at_config* c) {
   g.slab[0] = (int64_t)2 * g.M * c->p[0] * c->n[1] * c->n[2];
   g.slab[1] = (int64_t)2 * g.M * c->p[1] * c->n[0] * c->n[2];
   g.slab[2] = (int64_t)2 * g.M * c->p[2] * c->n[0] * c->n[1];
+  // components per published point: u, v, w, T and the face-normal flux, or the five conserved
+  // variables of the paper's form
+  const int ncomp = c->form == 1 ? kNQ : kNRing;
   g.ring_dir_off[0] = 0;
-  g.ring_dir_off[1] = kNRing * g.slab[0];
-  g.ring_dir_off[2] = kNRing * (g.slab[0] + g.slab[1]);
-  g.ring_slot = kNRing * (g.slab[0] + g.slab[1] + g.slab[2]);
+  g.ring_dir_off[1] = ncomp * g.slab[0];
+  g.ring_dir_off[2] = ncomp * (g.slab[0] + g.slab[1]);
+  g.ring_slot = ncomp * (g.slab[0] + g.slab[1] + g.slab[2]);
   g.R = c->max_delay + g.tl;
   g.ntiles = c->p[0] * c->p[1] * c->p[2];
   return g;
@@ -103,11 +120,13 @@ Layout make_layout(const at_config* c, const Geom& g) {
   L.dq = take(kNQ * N * w);
   L.ring = take((size_t)g.R * g.ring_slot * w);
   // the AT sums of the three stages of a step (fourth order); the flux buffer (sixth order)
-  L.gv = take(c->order == 4 ? (size_t)3 * g.ring_slot * w : 0);
+  L.gv = take(c->order == 4 && c->form == 0 ? (size_t)3 * g.ring_slot * w : 0);
   L.flux = take(c->order == 6 ? (size_t)3 * kNQ * N * w : 0);
+  L.grad = take(c->form == 1 ? (size_t)kNGrad * N * w : 0);
   // smallest tile (16 x 4) and smallest z chunk (4) bound the workgroup count of any stage launch
   L.ntot = (int64_t)((c->n[0] + 15) / 16) * ((c->n[1] + 3) / 4) * ((c->n[2] + 3) / 4);
   if (c->order == 6) L.ntot = std::max<int64_t>(L.ntot, blocks6(g));
+  if (c->form == 1) L.ntot = std::max<int64_t>(L.ntot, paper_blocks(g));
   L.tot_part = take((size_t)L.ntot * kNQ * 8);
   L.stat_part = take((size_t)stats_blocks(g) * kNStat * 8);
   L.stat_out = take(kStatOutBytes);
@@ -293,6 +312,44 @@ hipError_t launch_views(at_sim* s, const StageArgs<T>& a, int nst = 3) {
   return e;
 }
 
+// Arguments of the paper's form (form 1) at the current state and step.
+template <typename T>
+StagePArgs<T> basep(at_sim* s) {
+  StagePArgs<T> a{};
+  a.g = s->g;
+  a.cf = make_coef<T>(s);
+  a.q = (T*)(s->ws + s->L.q[s->qcur]);
+  a.q_out = (T*)(s->ws + s->L.q[1 - s->qcur]);
+  a.dq = (T*)(s->ws + s->L.dq);
+  a.grad = (T*)(s->ws + s->L.grad);
+  a.ring = (T*)(s->ws + s->L.ring);
+  a.tot_part = (double*)(s->ws + s->L.tot_part);
+  a.delays = s->d_sched ? s->d_sched + (size_t)s->step * s->g.ntiles * 6 : s->d_zero;
+  a.step_mod_r = (int)(s->step % s->g.R);
+  a.slot = a.step_mod_r;
+  a.mode = kModeStepH;
+  a.dt = (T)s->cfg.dt;
+  a.vol = (kTwoPi / s->cfg.n[0]) * (kTwoPi / s->cfg.n[1]) * (kTwoPi / s->cfg.n[2]);
+  return a;
+}
+
+template <typename T>
+hipError_t launchp_hooked(at_sim* s, const StagePArgs<T>& a, int which) {
+  const int id = which == kPPublish ? kKPPublish : (which == kPGrad ? kKPGrad : kKPRhs);
+  if (s->timer) s->timer->before(id, s->stream);
+  hipError_t e = launch_stagep<T>(a, which, s->stream);
+  if (s->timer) s->timer->after(id, s->stream);
+  return e;
+}
+
+// One RHS evaluation of the paper's form (its gradients, then every term and the update).
+template <typename T>
+hipError_t stagep(at_sim* s, const StagePArgs<T>& a) {
+  hipError_t e = launchp_hooked<T>(s, a, kPGrad);
+  if (e != hipSuccess) return e;
+  return launchp_hooked<T>(s, a, kPRhs);
+}
+
 template <typename T>
 int do_stats(at_sim* s, double* host_out) {
   const Coef<T> cf = make_coef<T>(s);
@@ -318,7 +375,11 @@ int do_init(at_sim* s, const double* q_host, int nlev) {
     HIP_TRY(hipMemcpyAsync(s->d_staging, q_host + (size_t)lev * kNQ * N, sizeof(double) * kNQ * N,
                            hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_convert<T>(s->d_staging, q, kNQ * N, s->stream));
-    if (lev < nlev - 1 && s->g.order == 6) {
+    if (lev < nlev - 1 && s->g.form == 1) {
+      StagePArgs<T> a = basep<T>(s);
+      a.slot = (int)(lev % s->g.R);
+      HIP_TRY(launchp_hooked<T>(s, a, kPPublish));
+    } else if (lev < nlev - 1 && s->g.order == 6) {
       Stage6Args<T> a = base6<T>(s);
       a.delays = s->d_zero;
       a.step_mod_r = (int)(lev % s->g.R);
@@ -370,8 +431,37 @@ int do_steps6(at_sim* s, int nsteps) {
   return AT_OK;
 }
 
+// The paper's form: publication at the start of each step, then per stage the gradients and the
+// right-hand side with the update (RK3), or one such stage per step (AB2, c_s = 0).
+template <typename T>
+int do_stepsp(at_sim* s, int nsteps, bool ab2) {
+  if (nsteps > 0) s->tot_used = std::max(s->tot_used, paper_blocks(s->g));
+  for (int it = 0; it < nsteps; ++it) {
+    HIP_TRY(launchp_hooked<T>(s, basep<T>(s), kPPublish));
+    for (int st = 0; st < (ab2 ? 1 : 3); ++st) {
+      StagePArgs<T> a = basep<T>(s);
+      if (ab2) {
+        a.rk_b = s->ab2_prev ? T(1.5) : T(1);
+        a.c_prev = s->ab2_prev ? T(-0.5) : T(0);
+        a.store_dq = 1;
+      } else {
+        a.cs = (T)kRkC[st];
+        a.rk_a = (T)kRkA[st];
+        a.rk_b = (T)kRkB[st];
+        a.store_dq = st < 2;
+      }
+      HIP_TRY(stagep<T>(s, a));
+      s->qcur = 1 - s->qcur;
+    }
+    s->ab2_prev = ab2 ? 1 : 0;
+    s->step++;
+  }
+  return AT_OK;
+}
+
 template <typename T>
 int do_steps(at_sim* s, int nsteps) {
+  if (s->g.form == 1) return do_stepsp<T>(s, nsteps, false);
   if (s->g.order == 6) return do_steps6<T>(s, nsteps);
   const size_t row = (size_t)s->g.ntiles * 6;
   if (nsteps > 0)
@@ -412,6 +502,7 @@ int do_steps(at_sim* s, int nsteps) {
 // (the Runge-Kutta update with A = 0, B = 1).
 template <typename T>
 int do_ab2_steps(at_sim* s, int nsteps) {
+  if (s->g.form == 1) return do_stepsp<T>(s, nsteps, true);
   if (s->g.order == 6) {
     if (nsteps > 0) s->tot_used = std::max(s->tot_used, blocks6(s->g));
     for (int it = 0; it < nsteps; ++it) {
@@ -459,6 +550,13 @@ int do_ab2_steps(at_sim* s, int nsteps) {
 
 template <typename T>
 int do_rhs(at_sim* s, void* out) {
+  if (s->g.form == 1) {
+    StagePArgs<T> a = basep<T>(s);
+    a.mode = kModeRhsH;
+    a.rhs_out = (T*)out;
+    HIP_TRY(stagep<T>(s, a));
+    return AT_OK;
+  }
   if (s->g.order == 6) {
     Stage6Args<T> a = base6<T>(s);
     a.mode = kModeRhsH;

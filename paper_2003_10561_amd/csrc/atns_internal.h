@@ -29,6 +29,7 @@ constexpr size_t kStatOutBytes = sizeof(double) * (kStatOutSlots + (size_t)kStat
 
 // Grid, virtual-PE tiling and ring geometry (shared by every kernel of one run).
 struct Geom {
+  int form;           // 0: total-energy flux form; 1: the paper's own discretisation (rho e)
   int order;          // spatial order: 4 or 6
   int M;              // layers each PE publishes per face (order / 2); the stencils' reach
   int tl;             // levels of one AT extrapolation (M + 1)
@@ -38,7 +39,7 @@ struct Geom {
   int64_t npts;
   int64_t slab[3];    // points of one direction's slab set: 2 M p_d n_a n_b
   int64_t ring_dir_off[3];  // element offset of direction d inside one ring slot
-  int64_t ring_slot;  // elements per ring slot = 9 * sum_d slab[d]
+  int64_t ring_slot;  // elements per ring slot = 9 * sum_d slab[d] (form 1: 5 * sum_d slab[d])
   int R;              // ring slots = max_delay + tl
   int ntiles;
 };
@@ -49,6 +50,9 @@ struct Coef {
   T inv12h[3];      // 1 / (12 h_d)
   T inv60h[3];      // 1 / (60 h_d)
   T gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
+  T suth_s;         // Sutherland's constant (visc = 1)
+  int visc;         // 0 power law, 1 Sutherland (form 1 only)
+  int form;         // 0 total energy E, 1 internal energy rho e as the fifth variable
 };
 
 // Forcing: per-step table A[pair][x][c] = sum_kx fhat(kx, pair, c) e^{i kx x} (complex), and the
@@ -140,8 +144,31 @@ constexpr int kModeStepH = 0, kModeRhsH = 1, kModePublishH = 2;
 // Kernel identities for timing (names in kernel_name()).
 enum KernelId {
   kKStage = 0, kKRhs = 1, kKPublish = 2, kKForce = 3, kKStats = 4, kKGhost = 5, kK6Grad = 6, kK6Div = 7,
-  kKCount = 8
+  kKPPublish = 8, kKPGrad = 9, kKPRhs = 10, kKCount = 11
 };
+
+// The paper's own discretisation (stagep.hip, form 1): publication of the conserved variables,
+// then per stage the AT gradients and the right-hand side with the update, one point per thread.
+template <typename T>
+struct StagePArgs {
+  Geom g;
+  Coef<T> cf;
+  T* q;
+  T* q_out;
+  T* dq;
+  T* grad;            // [12][N]
+  T* ring;            // R slots of 5 * sum_d slab[d]
+  T* rhs_out;
+  const int8_t* delays;
+  double* tot_part;
+  int step_mod_r, slot, store_dq, mode;
+  T cs, rk_a, rk_b, dt, c_prev;
+  double vol;
+};
+constexpr int kPPublish = 0, kPGrad = 1, kPRhs = 2;
+int64_t paper_blocks(const Geom& g);
+template <typename T>
+hipError_t launch_stagep(const StagePArgs<T>& s, int which, hipStream_t stream);
 
 // Sixth-order stage (stage6.hip): gradients and fluxes, then divergence and update; tiles of
 // bx x by columns inside one PE, one workgroup per (tile, z-PE).

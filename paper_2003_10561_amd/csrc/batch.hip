@@ -592,6 +592,7 @@ int at_batch_add(at_batch* b, at_sim* s) {
   if (s->device != b->device) return fail(AT_E_INVAL, "run and batch must be on the same device");
   if ((int)b->runs.size() >= kMaxBatchRuns) return fail(AT_E_INVAL, "batch is full");
   if (s->cfg.order != 4) return fail(AT_E_INVAL, "batched runs use the fourth-order scheme");
+  if (s->cfg.form != 0) return fail(AT_E_INVAL, "batched runs use the total-energy flux form");
   if (s->cfg.forcing && (fused_lds_bytes(b->tile, word_of(b->precision), true) > kLdsBytes ||
                          fused_lds_bytes(b->tile_d, word_of(b->precision), true) > kLdsBytes))
     return fail(AT_E_INVAL, "the batch's tile shape does not fit a forced run; set a smaller tile first");

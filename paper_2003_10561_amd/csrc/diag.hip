@@ -182,7 +182,8 @@ __global__ void k_twiddle(double2* tw, int ntw) {
 }
 
 struct Phys {
-  double inv_cv, gas_r, mu_ref, inv_tref, mu_exp;
+  double inv_cv, gas_r, mu_ref, inv_tref, mu_exp, suth_s;
+  int form, visc;   // fifth variable E (0) or rho e (1); power law (0) or Sutherland (1)
   double inv_h[3];  // 1 / (12 h) for order 4, 1 / (60 h) for order 6
 };
 
@@ -197,7 +198,8 @@ __device__ __forceinline__ void prims(const T* __restrict__ q, int64_t N, int64_
   pr[1] = u;
   pr[2] = v;
   pr[3] = w;
-  pr[4] = ((double)q[4 * N + i] * rinv - 0.5 * (u * u + v * v + w * w)) * ph.inv_cv;
+  pr[4] = ph.form == 1 ? (double)q[4 * N + i] * rinv * ph.inv_cv
+                       : ((double)q[4 * N + i] * rinv - 0.5 * (u * u + v * v + w * w)) * ph.inv_cv;
 }
 
 // Per-point values of one point: g = du/dx, eps, Omega, p (synchronous periodic derivatives).
@@ -232,7 +234,9 @@ __device__ __forceinline__ void point_values(const T* __restrict__ q, int nx, in
   const int64_t i = ((int64_t)z * ny + y) * nx + x;
   double pr[5];
   prims<T>(q, N, i, ph, pr);
-  const double mu = ph.mu_ref * pow(pr[4] * ph.inv_tref, ph.mu_exp);
+  const double tt = pr[4] * ph.inv_tref;
+  const double mu = ph.visc == 1 ? ph.mu_ref * tt * sqrt(tt) * (1.0 / ph.inv_tref + ph.suth_s) / (pr[4] + ph.suth_s)
+                                 : ph.mu_ref * pow(tt, ph.mu_exp);
   const double th = G[0] + G[4] + G[8];
   double e = 0.0;
 #pragma unroll
@@ -635,6 +639,9 @@ int run_diag(const at_config* cfg, const Plan& pl, const at_diag_params* prm, co
   ph.mu_ref = cfg->mu_ref;
   ph.inv_tref = 1.0 / cfg->t_ref;
   ph.mu_exp = cfg->mu_exp;
+  ph.suth_s = cfg->sutherland_s;
+  ph.form = cfg->form;
+  ph.visc = cfg->visc_law;
   for (int d = 0; d < 3; ++d) ph.inv_h[d] = 1.0 / ((M == 2 ? 12.0 : 60.0) * (kTwoPi / cfg->n[d]));
   double2* S = (double2*)(ws + pl.off_S);
   double2* tw = (double2*)(ws + pl.off_tw);

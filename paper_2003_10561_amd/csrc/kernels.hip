@@ -18,8 +18,9 @@ __device__ __forceinline__ float tpow<float>(float a, float b) { return powf(a, 
 
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// rho, u, v, w, T from the fifth variable E (form 0) or rho e (form 1, the paper's own form).
 template <typename T>
-__device__ __forceinline__ void primitives(const T* q, int64_t N, int64_t i, T inv_cv, T pr[5]) {
+__device__ __forceinline__ void primitives(const T* q, int64_t N, int64_t i, T inv_cv, int form, T pr[5]) {
   const T rho = q[i];
   const T rinv = T(1) / rho;
   const T u = q[N + i] * rinv, v = q[2 * N + i] * rinv, w = q[3 * N + i] * rinv;
@@ -27,7 +28,7 @@ __device__ __forceinline__ void primitives(const T* q, int64_t N, int64_t i, T i
   pr[1] = u;
   pr[2] = v;
   pr[3] = w;
-  pr[4] = (q[4 * N + i] * rinv - T(0.5) * (u * u + v * v + w * w)) * inv_cv;
+  pr[4] = form == 1 ? q[4 * N + i] * rinv * inv_cv : (q[4 * N + i] * rinv - T(0.5) * (u * u + v * v + w * w)) * inv_cv;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void k_stats(Geom g, Coef<T> cf, const T* __re
         r[d] = wrap1(pt[d] + m, g.n[d]);
         const int64_t ir = ((int64_t)r[2] * g.n[1] + r[1]) * g.n[0] + r[0];
         T pr[5];
-        primitives<T>(q, N, ir, cf.inv_cv, pr);
+        primitives<T>(q, N, ir, cf.inv_cv, cf.form, pr);
         v[mi][0] = pr[1];
         v[mi][1] = pr[2];
         v[mi][2] = pr[3];
@@ -77,8 +78,11 @@ __global__ __launch_bounds__(256) void k_stats(Geom g, Coef<T> cf, const T* __re
       }
     }
     T pr[5];
-    primitives<T>(q, N, i, cf.inv_cv, pr);
-    const double mu = (double)cf.mu_ref * pow((double)pr[4] * (double)cf.inv_tref, (double)cf.mu_exp);
+    primitives<T>(q, N, i, cf.inv_cv, cf.form, pr);
+    const double tt = (double)pr[4] * (double)cf.inv_tref;
+    const double mu = cf.visc == 1 ? (double)cf.mu_ref * tt * sqrt(tt) * (1.0 / (double)cf.inv_tref + (double)cf.suth_s) /
+                                         ((double)pr[4] + (double)cf.suth_s)
+                                   : (double)cf.mu_ref * pow(tt, (double)cf.mu_exp);
     const double th = (double)G[0] + (double)G[4] + (double)G[8];
     double eps = 0.0;
 #pragma unroll
@@ -266,7 +270,8 @@ int64_t stats_blocks(const Geom& g) { return update_blocks(g); }
 
 const char* kernel_name(int id) {
   static const char* names[kKCount] = {"k_stage", "k_stage(rhs)", "k_stage(publish)", "k_force_table",
-                                       "k_stats", "k_at_sums", "k6_gradflux", "k6_divupdate"};
+                                       "k_stats", "k_at_sums", "k6_gradflux", "k6_divupdate",
+                                       "kp_publish", "kp_grad", "kp_rhs"};
   return (id >= 0 && id < kKCount) ? names[id] : "";
 }
 

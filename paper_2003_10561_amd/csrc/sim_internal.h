@@ -29,7 +29,7 @@ inline size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Byte offsets of the workspace regions of one run.
 struct Layout {
-  size_t q[2], dq, ring, gv, flux, tot_part, stat_part, stat_out, force_table, phase_x, phase_y, phase_z, total;
+  size_t q[2], dq, ring, gv, flux, grad, tot_part, stat_part, stat_out, force_table, phase_x, phase_y, phase_z, total;
   int64_t ntot;  // FP64 total-accumulator slots (an upper bound on fused-stage workgroups)
 };
 
@@ -98,6 +98,9 @@ Coef<T> coef_of(const at_config& c) {
   cf.mu_ref = (T)c.mu_ref;
   cf.inv_tref = (T)(1.0 / c.t_ref);
   cf.mu_exp = (T)c.mu_exp;
+  cf.suth_s = (T)c.sutherland_s;
+  cf.visc = c.visc_law;
+  cf.form = c.form;
   return cf;
 }
 

@@ -70,8 +70,23 @@ def test_workspace_bytes_formula_order6(lib):
     assert need <= b64 <= 1.1 * need
 
 
+def test_workspace_bytes_formula_paper_form(lib):
+    """The paper's form: the ring holds the five conserved variables of the two face layers per side
+    (L + 3 levels) and a 12-component gradient buffer replaces the AT-sum buffers."""
+    b64 = atns.workspace_bytes(cfg(form=1))
+    N = 32 ** 3
+    phi = 4 * (1 / 16 + 1 / 16 + 1 / 32)
+    ring = (3 + 3) * 5 * phi * N
+    need = 8 * (5 + 5 + 5 + 12) * N + 8 * ring
+    assert need <= b64 <= 1.15 * need
+    assert atns.workspace_bytes(cfg(form=1, visc_law=1, sutherland_s=0.4)) == b64
+
+
 @pytest.mark.parametrize("bad", [dict(n=(30, 32, 32), p=(4, 2, 1)), dict(p=(16, 2, 1)), dict(order=8),
                                  dict(order=6, p=(8, 2, 1)), dict(order=6, forcing=True),
+                                 dict(form=2), dict(visc_law=1, sutherland_s=0.4), dict(form=1, visc_law=1),
+                                 dict(form=1, order=6), dict(form=1, forcing=True), dict(form=1, p=(8, 2, 1)),
+                                 dict(visc_law=2, form=1),
                                  dict(max_delay=9), dict(dt=0.0), dict(mu_ref=-1.0),
                                  dict(gamma=1.0), dict(precision="fp16x")])
 def test_invalid_config_rejected_without_gpu(lib, bad):
