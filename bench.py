@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cfg2", action="store_true", help="skip the decaying 256^3 FP64 configuration")
     ap.add_argument("--no-order6", action="store_true", help="skip the sixth-order scheme")
     ap.add_argument("--no-diag", action="store_true", help="skip the turbulence diagnostics of the final state")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's own discretisation (form 1)")
+    ap.add_argument("--no-paper-ab2", action="store_true", help="the paper's form: RK3 steps only (profiling)")
     ap.add_argument("--cfg2-steps", type=int, default=100)
     ap.add_argument("--tile", type=int, default=None, help="fused-stage tile shape (default: library)")
     ap.add_argument("--zchunk", type=int, default=None)
@@ -445,6 +447,60 @@ def decaying_cfg2(torch, atns, W, traffic, steps):
                         "statistics every step"}
 
 
+PAPER_KERNELS = ("kp_publish", "kp_grad", "kp_rhs")
+
+
+def paper_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K, with_ab2=True):
+    """The paper's own discretisation (internal-energy form, (2,4) AT second derivatives, three-step
+    mixed derivatives, Sutherland's law) on the same 512^3 field, FP32, unforced, CAA c_r = 4: RK3
+    steps (timed window, then a kernel-event window for the roofline), then AB2 steps, the paper's
+    own integrator."""
+    cv = W.GAS_R / (W.GAMMA - 1.0)
+    qp = q.copy()
+    qp[4] = q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]  # rho e = E - rho |u|^2 / 2
+    total = Wm + 3 * K + 4
+    cfg = atns.Config(n=(n,) * 3, p=(pe,) * 3, dt=dt, mu_ref=mu, max_delay=3, precision="fp32", form=1,
+                      visc_law=1, sutherland_s=0.4)
+    sim = atns.Sim(cfg)
+    sim.init_field(qp)
+    del qp
+    sim.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=total)
+    ms = time_window(torch, sim, K, warmup=Wm)
+    ms_ev, kt = kernel_window(torch, sim, K)
+    pd = sum(1 for s in range(Wm + K, Wm + 2 * K) if s >= 4 and s % 4) / K
+    stage_ms = sum(kt[k][0] for k in kt if k in PAPER_KERNELS) / (3 * K)
+    words = traffic.paper_words_per_point_step((n,) * 3, (pe,) * 3, pd) / 3.0
+    gbs = words * 4 * n ** 3 / (stage_ms * 1e-3) / 1e9
+    ab2 = None
+    if with_ab2:
+        sim.ab2_step(2)
+        ms_ab2, kt_ab2 = kernel_window(torch, sim, K, sim.ab2_step)
+        pd_ab2 = sum(1 for s in range(Wm + 2 * K + 4, Wm + 3 * K + 4) if s >= 4 and s % 4) / K
+        step_ab2 = sum(kt_ab2[k][0] for k in kt_ab2 if k in PAPER_KERNELS) / K
+        gbs_ab2 = traffic.paper_words_per_point_step((n,) * 3, (pe,) * 3, pd_ab2, ab2=True) * 4 * n ** 3 / (
+            step_ab2 * 1e-3) / 1e9
+        ab2 = {"value": n ** 3 * K / (ms_ab2 * 1e-3), "ms_per_step": ms_ab2 / K,
+               "roofline": {"bound": "hbm", "achieved": gbs_ab2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": gbs_ab2 / HBM_PEAK_GBS,
+                            "algorithmic_bytes_per_point_step":
+                                4 * traffic.paper_words_per_point_step((n,) * 3, (pe,) * 3, pd_ab2, ab2=True)},
+               "timing": "kernel events"}
+    st = sim.stats()
+    sim.close()
+    torch.cuda.empty_cache()
+    return {"value": n ** 3 * K / (ms * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms / K, "steps": K,
+            "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+            "roofline": {"bound": "hbm", "kernel": "+".join(PAPER_KERNELS), "achieved": gbs, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "avg_stage_ms": stage_ms,
+                         "algorithmic_bytes_per_point_step": words * 3 * 4,
+                         "traffic": measured_traffic(f"kp_stage_{n}_pe{pe}_fp32", "stagep.hip")},
+            "delayed_fraction": pd, "ab2": ab2,
+            "nonfinite": st["nonfinite"], "stats_after": {k: st[k] for k in ("K", "eps", "enstrophy", "Mt")},
+            "workload": f"decaying turbulence {n}^3, {pe}x{pe}x{pe} PEs, the paper's internal-energy form "
+                        "((2,4) AT second derivatives, three-step mixed derivatives, Sutherland S = 0.4), "
+                        "CAA L=3, FP32"}
+
+
 def diag_leg(torch, atns, sim, n, reps=3):
     """Turbulence diagnostics (Sec. 4.1: E(kappa), E_p(kappa), S and F of du/dx, PDFs of eps/<eps> and
     Omega/<Omega>) of the headline run's final FP32 state, timed with HIP events on the run's stream."""
@@ -599,6 +655,10 @@ def main():
         log("sixth-order scheme ...")
         out["order6"] = order6_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K)
         log(f"order6: {out['order6']}")
+    if not args.no_paper:
+        log("the paper's own discretisation ...")
+        out["paper_form"] = paper_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K, not args.no_paper_ab2)
+        log(f"paper_form: {out['paper_form']}")
     if not args.no_cfg2:
         log("decaying 256^3 FP64 configuration ...")
         out["decaying_256"] = decaying_cfg2(torch, atns, W, traffic, args.cfg2_steps)

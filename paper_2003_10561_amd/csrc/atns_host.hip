@@ -335,17 +335,18 @@ StagePArgs<T> basep(at_sim* s) {
 
 template <typename T>
 hipError_t launchp_hooked(at_sim* s, const StagePArgs<T>& a, int which) {
-  const int id = which == kPPublish ? kKPPublish : (which == kPGrad ? kKPGrad : kKPRhs);
+  const int id = which == kPPublish ? kKPPublish : (which == kPRhs ? kKPRhs : kKPGrad);
   if (s->timer) s->timer->before(id, s->stream);
   hipError_t e = launch_stagep<T>(a, which, s->stream);
   if (s->timer) s->timer->after(id, s->stream);
   return e;
 }
 
-// One RHS evaluation of the paper's form (its gradients, then every term and the update).
+// One RHS evaluation of the paper's form (its gradients, publishing level n at stage 1 of a step
+// when asked, then every term and the update).
 template <typename T>
-hipError_t stagep(at_sim* s, const StagePArgs<T>& a) {
-  hipError_t e = launchp_hooked<T>(s, a, kPGrad);
+hipError_t stagep(at_sim* s, const StagePArgs<T>& a, bool publish = false) {
+  hipError_t e = launchp_hooked<T>(s, a, publish ? kPGradPublish : kPGrad);
   if (e != hipSuccess) return e;
   return launchp_hooked<T>(s, a, kPRhs);
 }
@@ -437,7 +438,6 @@ template <typename T>
 int do_stepsp(at_sim* s, int nsteps, bool ab2) {
   if (nsteps > 0) s->tot_used = std::max(s->tot_used, paper_blocks(s->g));
   for (int it = 0; it < nsteps; ++it) {
-    HIP_TRY(launchp_hooked<T>(s, basep<T>(s), kPPublish));
     for (int st = 0; st < (ab2 ? 1 : 3); ++st) {
       StagePArgs<T> a = basep<T>(s);
       if (ab2) {
@@ -450,7 +450,7 @@ int do_stepsp(at_sim* s, int nsteps, bool ab2) {
         a.rk_b = (T)kRkB[st];
         a.store_dq = st < 2;
       }
-      HIP_TRY(stagep<T>(s, a));
+      HIP_TRY(stagep<T>(s, a, st == 0));
       s->qcur = 1 - s->qcur;
     }
     s->ab2_prev = ab2 ? 1 : 0;

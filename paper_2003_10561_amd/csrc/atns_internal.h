@@ -165,7 +165,7 @@ struct StagePArgs {
   T cs, rk_a, rk_b, dt, c_prev;
   double vol;
 };
-constexpr int kPPublish = 0, kPGrad = 1, kPRhs = 2;
+constexpr int kPPublish = 0, kPGrad = 1, kPRhs = 2, kPGradPublish = 3;
 int64_t paper_blocks(const Geom& g);
 template <typename T>
 hipError_t launch_stagep(const StagePArgs<T>& s, int which, hipStream_t stream);

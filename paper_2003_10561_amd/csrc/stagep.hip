@@ -11,11 +11,11 @@
 // standard fourth-order one-sided and biased stencils on the two points next to a face), then the
 // average.  Viscosity: the power law or Sutherland's law (Sec. 2).
 //
-// Launches: kp_publish (stage 1 of a step, or a history level: the conserved variables of every
-// PE's two layers next to each face into ring slot n mod R), then per stage kp_grad (the 12 AT
-// gradients of u, v, w, T into a workspace buffer) and kp_rhs (every term above at one point per
-// thread, the gradients of the PE-local mixed-derivative lines read back from that buffer, then
-// the Runge-Kutta or Adams-Bashforth update and FP64 block totals).
+// Launches: per stage kp_grad (the 12 AT gradients of u, v, w, T into a workspace buffer; at stage 1
+// of a step the points of every PE's two layers next to each face also publish their conserved
+// variables into ring slot n mod R) and kp_rhs (every term above at one point per thread, the
+// gradients of the PE-local mixed-derivative lines read back from that buffer, then the Runge-Kutta
+// or Adams-Bashforth update and FP64 block totals); kp_publish publishes a history level alone.
 #include "atns_internal.h"
 
 namespace atns {
@@ -178,78 +178,129 @@ __global__ __launch_bounds__(256) void kp_publish(PA<T> a) {
   for (int c = 0; c < 5; ++c) dst[(uint32_t)c * a.slab[d]] = a.q[(uint32_t)c * a.N + i];
 }
 
-// The 12 AT gradients of u, v, w, T at every point.
+// Workgroups: 64 x 4 columns marching through kZC planes (the z neighbours of a plane are read
+// again from the caches by the same threads), numbered XCD-major: the hardware deals consecutive
+// workgroups to the 8 XCDs in turn, so logical workgroup L = xcd_major(w) gives each XCD (one L2)
+// a contiguous range of bricks.
+constexpr int kZC = 16;
+constexpr uint32_t kNumXcd = 8;
+__device__ __forceinline__ uint32_t xcd_major(uint32_t w, uint32_t nb) {
+  const uint32_t c = w % kNumXcd, i = w / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
+  return c * q + min(c, r) + i;
+}
+
+struct Brick {
+  int x, y, z0, z1;
+  uint32_t L;
+};
 template <typename T>
-__global__ __launch_bounds__(256) void kp_grad(PA<T> a) {
-  const int x = blockIdx.x * kBXp + threadIdx.x, y = blockIdx.y * kBYp + threadIdx.y, z = blockIdx.z;
-  if (x >= a.n[0] || y >= a.n[1]) return;
-  const int p[3] = {x, y, z};
-  const int tile = (z / a.e[2] * a.p[1] + y / a.e[1]) * a.p[0] + x / a.e[0];
-  const uint32_t i = ((uint32_t)z * a.n[1] + y) * a.n[0] + x;
+__device__ __forceinline__ Brick brick(const PA<T>& a) {
+  const uint32_t gx = (uint32_t)(a.n[0] + kBXp - 1) / kBXp, gy = (uint32_t)(a.n[1] + kBYp - 1) / kBYp;
+  const uint32_t L = xcd_major(blockIdx.x, gridDim.x);
+  const uint32_t bz = L / (gx * gy), r = L - bz * gx * gy, by = r / gx, bx = r - by * gx;
+  Brick b;
+  b.x = (int)bx * kBXp + threadIdx.x;
+  b.y = (int)by * kBYp + threadIdx.y;
+  b.z0 = (int)bz * kZC;
+  b.z1 = min(b.z0 + kZC, a.n[2]);
+  b.L = L;
+  return b;
+}
+
+// The 12 AT gradients of u, v, w, T at every point; with `publish`, the points on the face layers
+// also write their conserved variables into ring slot a.slot (stage 1 of a step).
+template <typename T>
+__global__ __launch_bounds__(256) void kp_grad(PA<T> a, int publish) {
+  const Brick b = brick(a);
+  if (b.x >= a.n[0] || b.y >= a.n[1]) return;
+  for (int z = b.z0; z < b.z1; ++z) {
+    const int p[3] = {b.x, b.y, z};
+    const int tile = (z / a.e[2] * a.p[1] + b.y / a.e[1]) * a.p[0] + b.x / a.e[0];
+    const uint32_t i = ((uint32_t)z * a.n[1] + b.y) * a.n[0] + b.x;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T vm2[10], vm1[10], vp1[10], vp2[10];
-    seen(a, p, tile, d, -2, vm2);
-    seen(a, p, tile, d, -1, vm1);
-    seen(a, p, tile, d, 1, vp1);
-    seen(a, p, tile, d, 2, vp2);
+    for (int d = 0; d < 3; ++d) {
+      T g[4] = {T(0), T(0), T(0), T(0)};
+      const T c1[4] = {T(1), T(-8), T(8), T(-1)};
+      const int off[4] = {-2, -1, 1, 2};
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const T g = ((vm2[c] - T(8) * vm1[c]) + (T(8) * vp1[c] - vp2[c])) * a.i12h[d];
-      a.grad[(uint32_t)(c < 3 ? 3 * c + d : 9 + d) * a.N + i] = g;
+      for (int s = 0; s < 4; ++s) {
+        T v[10];
+        seen(a, p, tile, d, off[s], v);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g[c] += c1[s] * v[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.grad[(uint32_t)(c < 3 ? 3 * c + d : 9 + d) * a.N + i] = g[c] * a.i12h[d];
+    }
+    if (publish) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int l = p[d] % a.e[d];
+        if (l < 2 || l >= a.e[d] - 2) {
+          T* dst = a.ring + (uint32_t)a.slot * a.rslot + a.rdir[d] + slab_of(a, d, p, l);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) dst[(uint32_t)c * a.slab[d]] = a.q[(uint32_t)c * a.N + i];
+        }
+      }
     }
   }
 }
 
-// Every term of the right-hand side at one point per thread, then the update.
+// Every term of the right-hand side at one point per thread and plane, then the update.
 template <typename T>
 __global__ __launch_bounds__(256) void kp_rhs(PA<T> a) {
-  const int x = blockIdx.x * kBXp + threadIdx.x, y = blockIdx.y * kBYp + threadIdx.y, z = blockIdx.z;
-  const bool valid = x < a.n[0] && y < a.n[1];
+  const Brick b = brick(a);
+  const bool valid = b.x < a.n[0] && b.y < a.n[1];
   double tsum[5] = {0, 0, 0, 0, 0};
-  if (valid) {
-    const int p[3] = {x, y, z};
-    const int tile = (z / a.e[2] * a.p[1] + y / a.e[1]) * a.p[0] + x / a.e[0];
-    const uint32_t i = ((uint32_t)z * a.n[1] + y) * a.n[0] + x;
+  for (int z = b.z0; valid && z < b.z1; ++z) {
+    const int p[3] = {b.x, b.y, z};
+    const int tile = (z / a.e[2] * a.p[1] + b.y / a.e[1]) * a.p[0] + b.x / a.e[0];
+    const uint32_t i = ((uint32_t)z * a.n[1] + b.y) * a.n[0] + b.x;
     T qc[5], vc[10];
 #pragma unroll
     for (int c = 0; c < 5; ++c) qc[c] = a.q[(uint32_t)c * a.N + i];
     derive(a, qc, 0, vc);
-    T G[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) G[c] = a.grad[(uint32_t)c * a.N + i];
     T cont = T(0), conve = T(0), lapT = T(0), conv[3] = {T(0), T(0), T(0)}, lap[3] = {T(0), T(0), T(0)},
       pg[3], pure[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      T vm2[10], vm1[10], vp1[10], vp2[10];
-      seen(a, p, tile, d, -2, vm2);
-      seen(a, p, tile, d, -1, vm1);
-      seen(a, p, tile, d, 1, vp1);
-      seen(a, p, tile, d, 2, vp2);
-      auto d1 = [&](int c) { return ((vm2[c] - T(8) * vm1[c]) + (T(8) * vp1[c] - vp2[c])) * a.i12h[d]; };
-      auto d2 = [&](int c) {
-        return (((T(16) * vm1[c] - vm2[c]) - T(30) * vc[c]) + (T(16) * vp1[c] - vp2[c])) * a.i12h2[d];
-      };
-      cont += d1(5);
+      // the first-derivative rows (1, -8, 8, -1) / 12h and the second-derivative rows
+      // (-1, 16, -30, 16, -1) / 12h^2, accumulated one offset at a time
+      const T c1[4] = {T(1), T(-8), T(8), T(-1)}, c2[4] = {T(-1), T(16), T(16), T(-1)};
+      const int off[4] = {-2, -1, 1, 2};
+      T s1[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};  // m_d, uu_0d, uu_1d, uu_2d, eu_d, p
+      T s2[4] = {T(0), T(0), T(0), T(0)};              // u, v, w, T
+#pragma unroll 1  // one neighbour at a time: 116 VGPRs in FP32 (4 waves per SIMD) against 229 unrolled
+      for (int s = 0; s < 4; ++s) {
+        T v[10];
+        seen(a, p, tile, d, off[s], v);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s1[c] += c1[s] * v[5 + c];
+        s1[5] += c1[s] * v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s2[c] += c2[s] * v[c];
+      }
+      cont += s1[0] * a.i12h[d];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        conv[c] += d1(6 + c);
-        const T l2 = d2(c);
+        conv[c] += s1[1 + c] * a.i12h[d];
+        const T l2 = (s2[c] - T(30) * vc[c]) * a.i12h2[d];
         lap[c] += l2;
         if (c == d) pure[d] = l2;
       }
-      conve += d1(9);
-      pg[d] = d1(4);
-      lapT += d2(3);
+      conve += s1[4] * a.i12h[d];
+      pg[d] = s1[5] * a.i12h[d];
+      lapT += (s2[3] - T(30) * vc[3]) * a.i12h2[d];
     }
+    T G[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) G[c] = a.grad[(uint32_t)c * a.N + i];
     const T temp = vc[3], pres = vc[4];
     T dmu;
     const T mu = viscosity(a, temp, &dmu);
     const T kt = mu * a.cp_over_pr, dkt = dmu * a.cp_over_pr;
     const T th = G[0] + G[4] + G[8];
-    const int lx = x % a.e[0], ly = y % a.e[1], lz = z % a.e[2];
-    const int loc[3] = {lx, ly, lz};
+    const int loc[3] = {b.x % a.e[0], b.y % a.e[1], z % a.e[2]};
     T rhs[5];
     rhs[0] = -cont;
 #pragma unroll
@@ -288,7 +339,7 @@ __global__ __launch_bounds__(256) void kp_rhs(PA<T> a) {
         const T inc = a.rk_b * dqv + a.c_prev * prev;
         if (a.store_dq) a.dq[(uint32_t)c * a.N + i] = dqv;
         a.q_out[(uint32_t)c * a.N + i] = qc[c] + inc;
-        tsum[c] = a.c_prev != T(0) ? (double)inc : (double)dqv;
+        tsum[c] += a.c_prev != T(0) ? (double)inc : (double)dqv;
       }
     }
   }
@@ -302,9 +353,8 @@ __global__ __launch_bounds__(256) void kp_rhs(PA<T> a) {
   __syncthreads();
   const int tid = threadIdx.y * kBXp + threadIdx.x;
   if (tid < 5) {
-    const uint32_t blk = ((uint32_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const double scale = a.c_prev != T(0) ? 1.0 : (double)a.rk_b;
-    a.tot_part[blk * kNQ + tid] += scale * ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) * a.vol;
+    a.tot_part[b.L * kNQ + tid] += scale * ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) * a.vol;
   }
 }
 
@@ -359,7 +409,7 @@ PA<T> pack(const StagePArgs<T>& s) {
 }  // namespace
 
 int64_t paper_blocks(const Geom& g) {
-  return (int64_t)((g.n[0] + kBXp - 1) / kBXp) * ((g.n[1] + kBYp - 1) / kBYp) * g.n[2];
+  return (int64_t)((g.n[0] + kBXp - 1) / kBXp) * ((g.n[1] + kBYp - 1) / kBYp) * ((g.n[2] + kZC - 1) / kZC);
 }
 
 template <typename T>
@@ -370,8 +420,9 @@ hipError_t launch_stagep(const StagePArgs<T>& s, int which, hipStream_t stream) 
     hipLaunchKernelGGL((kp_publish<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
   }
-  const dim3 grid((s.g.n[0] + kBXp - 1) / kBXp, (s.g.n[1] + kBYp - 1) / kBYp, s.g.n[2]);
-  if (which == kPGrad) hipLaunchKernelGGL((kp_grad<T>), grid, dim3(kBXp, kBYp), 0, stream, a);
+  const dim3 grid((unsigned)paper_blocks(s.g));
+  if (which == kPGrad || which == kPGradPublish)
+    hipLaunchKernelGGL((kp_grad<T>), grid, dim3(kBXp, kBYp), 0, stream, a, which == kPGradPublish ? 1 : 0);
   else hipLaunchKernelGGL((kp_rhs<T>), grid, dim3(kBXp, kBYp), 0, stream, a);
   return hipGetLastError();
 }

@@ -27,12 +27,17 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 STAGE = "k_stage<"  # defaults; main() takes --stage / --aux
-VIEWS = "k_at_sums<"
+VIEWS = ("k_at_sums<",)
+
+
+def is_aux(k):
+    return STAGE not in k and any(v in k for v in VIEWS)
 
 
 def short_name(k):
     """Kernel name without return type, namespaces and argument list."""
     k = k.replace("void ", "").replace("atns::(anonymous namespace)::", "").replace("atns::", "")
+    k = k.replace("(anonymous namespace)::", "")
     return k.split("(")[0]
 
 
@@ -62,7 +67,7 @@ def timed_window(seq, timed):
         raise ValueError(f"only {len(idx)} stage launches")
     first = idx[-timed]
     # the auxiliary launches of a stage come just before its stage launch
-    while first > 0 and VIEWS in seq[first - 1][0]:
+    while first > 0 and is_aux(seq[first - 1][0]):
         first -= 1
     last = idx[-1]
     return seq[first:last + 1]
@@ -90,17 +95,20 @@ def main():
     ap.add_argument("--timed", type=int, required=True)
     ap.add_argument("--workload", default="")
     ap.add_argument("--stage", default="k_stage<")
-    ap.add_argument("--aux", default="k_at_sums<")
+    ap.add_argument("--aux", default="k_at_sums<", help="comma-separated patterns of the auxiliary launches")
+    ap.add_argument("--summary", default="", help="comma-separated kernel patterns: per-kernel table only")
     ap.add_argument("--source", default="stage_fused.hip", help="kernel source whose sha256 is recorded")
     a = ap.parse_args()
     global STAGE, VIEWS, SOURCE
-    STAGE, VIEWS, SOURCE = a.stage, a.aux, a.source
+    STAGE, VIEWS, SOURCE = a.stage, tuple(a.aux.split(",")), a.source
+    if a.summary:
+        return summary(a)
 
     seq = dispatches(a.trace)
     win = timed_window(seq, a.timed)
     st_ms = sum(d for k, d in win if STAGE in k)
-    gv_ms = sum(d for k, d in win if VIEWS in k)
-    n_gv = sum(1 for k, _ in win if VIEWS in k)
+    gv_ms = sum(d for k, d in win if is_aux(k))
+    n_gv = sum(1 for k, _ in win if is_aux(k))
     def table(entries, top):
         per_kernel = {}
         for k, d in entries:
@@ -111,7 +119,7 @@ def main():
             rows.append(f"| `{short_name(k)[:80]}` | {c} | {t / c:.3f} | {t:.1f} |")
         return rows
 
-    lines = [f"# Kernel trace: {STAGE.rstrip('<')} and {VIEWS.rstrip('<')}, {a.workload}", "",
+    lines = [f"# Kernel trace: {STAGE.rstrip('<')} and {', '.join(v.rstrip('<') for v in VIEWS)}, {a.workload}", "",
              "Command (R = the repository root; run from /tmp with `export TMPDIR=/tmp`):", "",
              "```", a.command.split(" ;; ")[0], "```", "",
              f"Kernels of the timed window (the last {a.timed} stage launches of the single-run workload):", ""]
@@ -120,7 +128,7 @@ def main():
     lines += table(seq, 12)
     lines += ["", f"Timed window (last {a.timed} stage launches):", "",
               f"- stage_launch: {STAGE.rstrip('<')}",
-              f"- aux_launch: {VIEWS.rstrip('<')}",
+              f"- aux_launch: {', '.join(v.rstrip('<') for v in VIEWS)}",
               f"- stage_launch_avg_ms: {st_ms / a.timed:.4f}",
               f"- aux_launches: {n_gv}",
               f"- aux_ms_per_stage: {gv_ms / a.timed:.4f}",
@@ -133,19 +141,20 @@ def main():
     fw = copy_factor(a.copy_write, a.copy_bytes)
     fetch = timed_window(counters(a.fetch), a.timed)
     write = timed_window(counters(a.write), a.timed)
-    fb = sum(v for k, v in fetch if STAGE in k or VIEWS in k) * 1024.0 * ff / a.timed
-    wb = sum(v for k, v in write if STAGE in k or VIEWS in k) * 1024.0 * fw / a.timed
+    fb = sum(v for k, v in fetch if STAGE in k or is_aux(k)) * 1024.0 * ff / a.timed
+    wb = sum(v for k, v in write if STAGE in k or is_aux(k)) * 1024.0 * fw / a.timed
     sf = [v * 1024.0 * ff for k, v in fetch if STAGE in k]
     sw = [v * 1024.0 * fw for k, v in write if STAGE in k]
     cmds = a.command.split(" ;; ")
-    lines = [f"# HBM traffic: {STAGE.rstrip('<')} and {VIEWS.rstrip('<')}, {a.workload}", "",
+    lines = [f"# HBM traffic: {STAGE.rstrip('<')} and {', '.join(v.rstrip('<') for v in VIEWS)}, {a.workload}", "",
              "Commands (R = the repository root; run from /tmp with `export TMPDIR=/tmp`):", "", "```"]
     lines += cmds[1:] if len(cmds) > 1 else cmds
     lines += ["```", "",
               f"Copy calibration: for a device copy of {a.copy_bytes:.0f} bytes each way, bytes moved / "
               f"bytes reported is {ff:.4f} for FETCH_SIZE and {fw:.4f} for WRITE_SIZE; these factors scale "
               "the stage counters below.", "",
-              f"Per stage over the timed window ({STAGE.rstrip('<')} plus {VIEWS.rstrip('<')}):", "",
+              f"Per stage over the timed window ({STAGE.rstrip('<')} plus {', '.join(v.rstrip('<') for v in VIEWS)}):",
+              "",
               f"- fetch_bytes_per_launch: {fb:.6e}",
               f"- write_bytes_per_launch: {wb:.6e}",
               f"- bytes_per_launch: {fb + wb:.6e}",
@@ -158,6 +167,32 @@ def main():
         lines.append(f"| {i} | {x / 1e9:.3f} | {y / 1e9:.3f} |")
     with open(a.out + "_traffic.md", "w") as f:
         f.write("\n".join(lines) + "\n")
+
+
+def summary(a):
+    """Per-kernel calls and durations over the whole traced run for the kernels matching the
+    --summary patterns (workloads measured per call rather than per stage)."""
+    pats = a.summary.split(",")
+    per = {}
+    for k, d in dispatches(a.trace):
+        if any(p in k for p in pats):
+            c, t = per.get(k, (0, 0.0))
+            per[k] = (c + 1, t + d)
+    rows = ["| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
+    tot = 0.0
+    for k, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        rows.append(f"| `{short_name(k)[:80]}` | {c} | {t / c:.3f} | {t:.1f} |")
+        tot += t
+    calls = max((c for c, _ in per.values()), default=0)
+    lines = [f"# Kernel trace: {a.workload}", "",
+             "Command (R = the repository root; run from /tmp with `export TMPDIR=/tmp`):", "",
+             "```", a.command, "```", "", "Kernels matching " + ", ".join(f"`{p}`" for p in pats) + ":", ""]
+    lines += rows
+    lines += ["", f"- calls_per_kernel: {calls}",
+              f"- ms_per_call_sum_of_kernels: {tot / max(calls, 1):.4f}",
+              f"- source_sha256: {source_sha()}", ""]
+    with open(a.out + "_trace.md", "w") as f:
+        f.write("\n".join(lines))
 
 
 if __name__ == "__main__":

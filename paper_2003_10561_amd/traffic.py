@@ -48,6 +48,16 @@ def ab2_words_per_point_step(n, p, p_delayed: float) -> float:
     return 20.0 + 9.0 * phi + 27.0 * phi * p_delayed
 
 
+def paper_words_per_point_step(n, p, p_delayed: float, ab2: bool = False) -> float:
+    """The paper's own discretisation (form 1): the RK3 state and register traffic (50 words; 20 for
+    an Adams-Bashforth step), the publication of the five conserved variables on the face layers
+    (5 phi) and, behind delayed faces, 3 levels of those 5 words read once per step (15 phi p_d).
+    The gradients that the mixed derivatives differentiate again are not algorithmic traffic (a
+    kernel could keep them on chip); this implementation writes and reads them (24 words a stage)."""
+    phi = ghost_fraction(n, p)
+    return (20.0 if ab2 else 50.0) + 5.0 * phi + 15.0 * phi * p_delayed
+
+
 def delayed_fraction(table) -> float:
     """Fraction of (step, PE, face) entries with delay >= 1 in an int8 schedule table."""
     import numpy as np

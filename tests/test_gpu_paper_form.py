@@ -157,3 +157,26 @@ def test_paper_form_error_paths():
     with pytest.raises(atns.AtError):
         g.rk_step(1)  # no schedule yet
     g.close()
+
+
+@pytest.mark.slow
+def test_paper_bench_pe_shape_fp32():
+    """The benchmark's PE shape (64^3 PEs; here 128^3 on 2 x 2 x 2), FP32, Sutherland's law, CAA
+    c_r = 4 past the ring wrap (8 steps), against the FP64 oracle: fields within 2e-6."""
+    n, p = (128, 128, 128), (2, 2, 2)
+    say("case paper-form 128^3 on 64^3 PEs fp32, 8 CAA steps")
+    q = turbulent_paper_state(128, 13)
+    dt, mu = W.default_dt(q), W.default_mu(128)
+    g, o = pair(n, p, dt, mu, precision="fp32", visc=1, suth=0.4)
+    for s in (g, o):
+        s.init_field(q)
+    g.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=10)
+    o.set_schedule(CAA, L=3, c_r=4, n_steps=10)
+    g.rk_step(8)
+    o.rk_step(8)
+    got, ref = g.get_field(), o.field()
+    errs = [rel_l2(got[c], ref[c]) for c in range(5)]
+    say("  field rel-L2: " + " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) <= 2e-6
+    compare_stats(g.stats(), o.stats(), 2e-5)
+    g.close()
