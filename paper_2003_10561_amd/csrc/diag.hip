@@ -126,17 +126,24 @@ __device__ __forceinline__ void dft8(double2* x) {
   x[7] = csub(e3, o3);
 }
 
+// LDS position of element e of an x line: one pad element after every 8, so that the strided
+// butterflies of the later stages (inputs 8 or 1 elements apart, 128 bytes and more) spread over
+// the banks instead of falling on the same half of them (the lines of the y and z passes are
+// interleaved by column, where those strides already fall on different banks).
+__device__ __forceinline__ int pe(int e) { return e + (e >> 3); }
+__host__ __device__ constexpr int padded(int n) { return n + n / 8; }
+
 // One in-place decimation-in-frequency stage of radix R = 2^LR on every line: span L, butterfly
 // inputs Ls = L / R apart; output t of butterfly j is multiplied by exp(-2 pi i j t / L).  Element
-// e of line l lives at buf[l * ls + e * es].  line_fast: consecutive threads take consecutive lines
+// e of line l lives at buf[l * ls + e' * es], e' = pe(e) with PAD, else e.  line_fast: consecutive threads take consecutive lines
 // (strided axes, where the lines are interleaved), else consecutive butterflies of one line.
-template <int LR>
+template <int LR, int NT, bool PAD>
 __device__ __forceinline__ void dif_stage(double2* buf, const Axis& a, int L, int nlines, int ls, int es,
                                           const double2* __restrict__ tw, bool line_fast) {
   constexpr int R = 1 << LR;
   const int Ls = L >> LR, nb = a.n >> LR, total = nlines * nb;
   const int twstep = (a.n / L) * a.tws;
-  for (int t = threadIdx.x; t < total; t += kThreads) {
+  for (int t = threadIdx.x; t < total; t += NT) {
     int line, b;
     if (line_fast) {
       line = t % nlines;
@@ -146,27 +153,29 @@ __device__ __forceinline__ void dif_stage(double2* buf, const Axis& a, int L, in
       line = t / nb;
     }
     const int blk = b / Ls, j = b - blk * Ls;
-    double2* base = buf + line * ls + (blk * L + j) * es;
+    double2* base = buf + line * ls;
+    const int e0 = blk * L + j;
     double2 x[R];
 #pragma unroll
-    for (int s = 0; s < R; ++s) x[s] = base[s * Ls * es];
+    for (int s = 0; s < R; ++s) x[s] = base[(PAD ? pe(e0 + s * Ls) : e0 + s * Ls) * es];
     if constexpr (R == 8) dft8(x);
     else if constexpr (R == 4) dft4(x[0], x[1], x[2], x[3]);
     else dft2(x[0], x[1]);
 #pragma unroll
     for (int s = 1; s < R; ++s) x[s] = cmul(x[s], tw[j * s * twstep]);
 #pragma unroll
-    for (int s = 0; s < R; ++s) base[s * Ls * es] = x[s];
+    for (int s = 0; s < R; ++s) base[(PAD ? pe(e0 + s * Ls) : e0 + s * Ls) * es] = x[s];
   }
 }
 
+template <int NT, bool PAD>
 __device__ void fft_lines(double2* buf, const Axis& a, int nlines, int ls, int es, const double2* __restrict__ tw,
                           bool line_fast) {
   int L = a.n;
   for (int i = 0; i < a.nst; ++i) {
-    if (a.lr[i] == 3) dif_stage<3>(buf, a, L, nlines, ls, es, tw, line_fast);
-    else if (a.lr[i] == 2) dif_stage<2>(buf, a, L, nlines, ls, es, tw, line_fast);
-    else dif_stage<1>(buf, a, L, nlines, ls, es, tw, line_fast);
+    if (a.lr[i] == 3) dif_stage<3, NT, PAD>(buf, a, L, nlines, ls, es, tw, line_fast);
+    else if (a.lr[i] == 2) dif_stage<2, NT, PAD>(buf, a, L, nlines, ls, es, tw, line_fast);
+    else dif_stage<1, NT, PAD>(buf, a, L, nlines, ls, es, tw, line_fast);
     L >>= a.lr[i];
     __syncthreads();
   }
@@ -405,22 +414,23 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_fft_x(const T* __restrict__ q, int nx, int64_t N, int rows, Axis ax,
                                                const double2* __restrict__ tw, Phys ph, double2* __restrict__ S,
                                                int px, int64_t fstride) {
-  extern __shared__ double2 lds[];  // [rows][2][nx]
+  extern __shared__ double2 lds[];  // [rows][2][padded(nx)]
   const int64_t row0 = (int64_t)blockIdx.x * rows;
+  const int lx = padded(nx);
   for (int t = threadIdx.x; t < rows * nx; t += kThreads) {
     const int r = t / nx, x = t - r * nx;
     double pr[5];
     prims<T>(q, N, (row0 + r) * nx + x, ph, pr);
-    lds[(2 * r) * nx + x] = make_double2(pr[1], pr[2]);
-    lds[(2 * r + 1) * nx + x] = make_double2(pr[3], pr[0] * ph.gas_r * pr[4]);
+    lds[(2 * r) * lx + pe(x)] = make_double2(pr[1], pr[2]);
+    lds[(2 * r + 1) * lx + pe(x)] = make_double2(pr[3], pr[0] * ph.gas_r * pr[4]);
   }
   __syncthreads();
-  fft_lines(lds, ax, 2 * rows, nx, 1, tw, false);
+  fft_lines<kThreads, true>(lds, ax, 2 * rows, lx, 1, tw, false);
   const int nh = nx / 2 + 1;
   for (int t = threadIdx.x; t < 2 * rows * nh; t += kThreads) {
     const int kx = t % nh, rl = t / nh;
-    const double2* line = lds + rl * nx;
-    const double2 zk = line[pos_of(ax, kx)], zm = line[pos_of(ax, (nx - kx) & (nx - 1))];
+    const double2* line = lds + rl * lx;
+    const double2 zk = line[pe(pos_of(ax, kx))], zm = line[pe(pos_of(ax, (nx - kx) & (nx - 1)))];
     const double2 A = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
     const double2 B = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
     const int f = 2 * (rl & 1);
@@ -431,19 +441,20 @@ __global__ __launch_bounds__(256) void k_fft_x(const T* __restrict__ q, int nx, 
 }
 
 // In-place transform along y of the columns kx0 .. kx0 + bx - 1 of one (field, z) plane.
-__global__ __launch_bounds__(256) void k_fft_y(double2* __restrict__ S, int nx, int ny, int px, int bx, Axis ay,
-                                               const double2* __restrict__ tw, int64_t fstride) {
+constexpr int kThreadsYZ = 512;  // 8 waves: twice the loads in flight of a 256-thread workgroup
+__global__ __launch_bounds__(kThreadsYZ) void k_fft_y(double2* __restrict__ S, int nx, int ny, int px, int bx, Axis ay,
+                                                      const double2* __restrict__ tw, int64_t fstride) {
   extern __shared__ double2 lds[];  // [ny][bx]
   const int kx0 = blockIdx.x * bx, z = blockIdx.y, f = blockIdx.z;
   const int nv = min(bx, nx / 2 + 1 - kx0);
   double2* base = S + f * fstride + (int64_t)z * ny * px + kx0;
-  for (int t = threadIdx.x; t < ny * bx; t += kThreads) {
+  for (int t = threadIdx.x; t < ny * bx; t += kThreadsYZ) {
     const int y = t / bx, l = t - y * bx;
     lds[t] = l < nv ? base[(int64_t)y * px + l] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines(lds, ay, bx, 1, bx, tw, true);
-  for (int t = threadIdx.x; t < ny * bx; t += kThreads) {
+  fft_lines<kThreadsYZ, false>(lds, ay, bx, 1, bx, tw, true);
+  for (int t = threadIdx.x; t < ny * bx; t += kThreadsYZ) {
     const int y = t / bx, l = t - y * bx;
     if (l < nv) base[(int64_t)y * px + l] = lds[t];
   }
@@ -462,7 +473,7 @@ __device__ __forceinline__ int shell_of(int k2) {
   return k2 > s * s + s ? s + 1 : s;
 }
 
-constexpr int kMaxPerThread = kLdsFft / (int)sizeof(double2) / kThreads;  // points per thread in the z pass
+constexpr int kMaxPerThread = kLdsFft / (int)sizeof(double2) / kThreadsYZ;  // points per thread in the z pass
 
 // Transform along z of the columns kx0 .. kx0 + bx - 1 of one (field, y-position) row, then the
 // workgroup's shell sums.  |S|^2 of every point (times 2 on the columns 0 < kx < nx/2, whose mirror
@@ -472,7 +483,7 @@ constexpr int kMaxPerThread = kLdsFft / (int)sizeof(double2) / kThreads;  // poi
 // ascending) and both halves of kz (kz >= 0, then kz < 0, |kz| ascending) with no atomics.
 // part[wg][j] is shell lo + j, hdr[wg] = (lo, count); velocity fields carry the factor 1/2 of the
 // energy.  |k|^2 <= 3 (n/2)^2 < 2^24 for n <= 1024.
-__global__ __launch_bounds__(256) void k_fft_z_shell(const double2* __restrict__ S, int nx, int ny, int nz, int px,
+__global__ __launch_bounds__(kThreadsYZ) void k_fft_z_shell(const double2* __restrict__ S, int nx, int ny, int nz, int px,
                                                      int bx, Axis ay, Axis az, const double2* __restrict__ tw,
                                                      int64_t fstride, int nshell, int spanmax,
                                                      double* __restrict__ part, int* __restrict__ hdr,
@@ -482,18 +493,18 @@ __global__ __launch_bounds__(256) void k_fft_z_shell(const double2* __restrict__
   const int nv = min(bx, nx / 2 + 1 - kx0);
   const double2* base = S + f * fstride + (int64_t)py * px + kx0;
   const int64_t zs = (int64_t)ny * px;
-  for (int t = threadIdx.x; t < nz * bx; t += kThreads) {
+  for (int t = threadIdx.x; t < nz * bx; t += kThreadsYZ) {
     const int z = t / bx, l = t - z * bx;
     lds[t] = l < nv ? base[z * zs + l] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines(lds, az, bx, 1, bx, tw, true);
+  fft_lines<kThreadsYZ, false>(lds, az, bx, 1, bx, tw, true);
   const int nzp = nz + 1;
   double ev[kMaxPerThread];
   int ei[kMaxPerThread];
 #pragma unroll
   for (int c = 0; c < kMaxPerThread; ++c) {
-    const int t = threadIdx.x + c * kThreads;
+    const int t = threadIdx.x + c * kThreadsYZ;
     ei[c] = -1;
     if (t < nz * bx) {
       const int p = t / bx, l = t - p * bx;
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(256) void k_fft_z_shell(const double2* __restrict__
     hdr[2 * wg + 1] = span;
   }
   const double scale = (f < 3 ? 0.5 : 1.0) * inv_n2;
-  for (int j = threadIdx.x; j < span; j += kThreads) {
+  for (int j = threadIdx.x; j < span; j += kThreadsYZ) {
     const int s = s_lo + j;
     const int lo2 = s == 0 ? 0 : s * s - s + 1, hi2 = s * s + s;
     double tot = 0.0;
@@ -675,12 +686,12 @@ int run_diag(const at_config* cfg, const Plan& pl, const at_diag_params* prm, co
   const Axis ax = make_axis(pl.nx, pl.ntw), ay = make_axis(pl.ny, pl.ntw), az = make_axis(pl.nz, pl.ntw);
   const int64_t nrows = (int64_t)pl.ny * pl.nz;
   hipLaunchKernelGGL((k_fft_x<T>), dim3((unsigned)(nrows / pl.rows)), dim3(kThreads),
-                     (size_t)pl.rows * 2 * pl.nx * sizeof(double2), st, q, pl.nx, N, pl.rows, ax,
+                     (size_t)pl.rows * 2 * padded(pl.nx) * sizeof(double2), st, q, pl.nx, N, pl.rows, ax,
                      (const double2*)tw, ph, S, pl.px, fstride);
-  hipLaunchKernelGGL(k_fft_y, dim3(pl.nbxy, pl.nz, 4), dim3(kThreads), (size_t)pl.ny * pl.bxy * sizeof(double2), st,
+  hipLaunchKernelGGL(k_fft_y, dim3(pl.nbxy, pl.nz, 4), dim3(kThreadsYZ), (size_t)pl.ny * pl.bxy * sizeof(double2), st,
                      S, pl.nx, pl.ny, pl.px, pl.bxy, ay, (const double2*)tw, fstride);
   const double inv_n2 = 1.0 / ((double)N * (double)N);
-  hipLaunchKernelGGL(k_fft_z_shell, dim3(pl.nbxz, pl.ny, 4), dim3(kThreads), (size_t)pl.nz * pl.bxz * sizeof(double2),
+  hipLaunchKernelGGL(k_fft_z_shell, dim3(pl.nbxz, pl.ny, 4), dim3(kThreadsYZ), (size_t)pl.nz * pl.bxz * sizeof(double2),
                      st, (const double2*)S, pl.nx, pl.ny, pl.nz, pl.px, pl.bxz, ay, az, (const double2*)tw, fstride,
                      nshell, (int)pl.spanmax, spart, hdr, inv_n2);
   hipLaunchKernelGGL(k_shell_reduce1, dim3(kRed), dim3(kThreads), 0, st, (const double*)spart, (const int*)hdr,
