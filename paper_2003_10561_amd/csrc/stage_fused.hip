@@ -172,8 +172,10 @@ __device__ __forceinline__ uint32_t zero_after(T v) {
 
 // v in a register of its own (FP32): the window keeps rho and E of a plane, and as copies of the
 // state registers they would hold those until the end of the iteration, past the refill.
-__device__ __forceinline__ float own_copy(float v) {
-  float r;
+template <typename T>
+__device__ __forceinline__ T own_copy(T v) {
+  static_assert(sizeof(T) == 4, "a copy into one 32-bit register");
+  T r;
   asm volatile("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
   return r;
 }
@@ -229,8 +231,10 @@ __device__ __forceinline__ void add5(T acc[kNQ], int c, T val) {
 
 // Per-column window of the z march: u, v, w, T of planes zc-2 .. zc+2 (index j = 0 .. 4) and rho,
 // E of plane zc, for the current plane zc; push() brings in plane zc + 3 and advances zc.  FP32
-// keeps it in registers (shifted one plane per push), FP64 in a thread-private LDS ring (slot z
-// mod 5, z mod 3), where registers are scarcer.
+// keeps it in registers (shifted one plane per push), and so do the FP64 stages without AT
+// stencils (they fit 2 waves per SIMD without spills, and the LDS freed lets 2 workgroups share a
+// CU); the FP64 AT stages keep it in a thread-private LDS ring (slot z mod 5, z mod 3), since in
+// registers they would spill.
 template <typename T, int NCOL, bool REG>
 struct ZWin;
 
@@ -329,7 +333,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   __shared__ T s_fx[2][5][BY][BX + 4];   // F_x on the tile rows, x halo 2
   __shared__ T s_fy[2][5][BY + 4][BX];   // F_y on the tile columns, y halo 2
   __shared__ double s_tsum[kNQ][TL::NOWN];  // FP64 running sums of dQ per tile column
-  constexpr bool kRegWin = sizeof(T) == 4;
+  constexpr bool kRegWin = sizeof(T) == 4 || !AT;
   __shared__ T s_win[kRegWin ? 1 : 26][kRegWin ? 1 : TL::NCOL];
   extern __shared__ unsigned char s_dyn[];  // forcing coefficients when forced
   T* s_force = reinterpret_cast<T*>(s_dyn);
@@ -963,7 +967,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       if (column) {
         T r_, u_, v_, w_, e_ = raw[4];
         prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
-        if constexpr (kRegWin) {
+        if constexpr (kRegWin && sizeof(T) == 4) {
           r_ = own_copy(r_);
           e_ = own_copy(e_);
         }
@@ -1128,13 +1132,24 @@ constexpr int sub_waves(int minw) {
 }
 
 // Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950); the halo AT-sum
-// slots of the aligned-tile instantiations are counted for all.
+// slots of the aligned-tile instantiations, and the FP64 LDS window of the AT ones, are counted for
+// all.
 template <typename T, int BX, int BY>
 constexpr size_t stage_static_lds() {
   using TL = Tile<BX, BY>;
   return sizeof(T) * (2 * (4 * TL::LH * TL::LW + 5 * BY * (BX + 4) + 5 * (BY + 4) * BX) +
                       (sizeof(T) == 4 ? 1 : 26 * TL::NCOL) + 4 * (TL::NY2 + TL::NX2)) +
          8 * kNQ * TL::NOWN;
+}
+
+// Occupancy target of the FP64 AT instantiations: no more waves per SIMD than their static LDS
+// (the LDS window) leaves room for, so that they keep the registers of that occupancy.
+template <typename T, int BX, int BY>
+constexpr int fp64_at_cap(int m) {
+  constexpr int nw = Tile<BX, BY>::NT / 64;
+  constexpr int wgs = (int)(kLdsBytes / stage_static_lds<T, BX, BY>());
+  constexpr int cap = (wgs * nw + 3) / 4 < 1 ? 1 : (wgs * nw + 3) / 4;
+  return sizeof(T) == 4 || m <= cap ? m : cap;
 }
 
 template <typename T, int BX, int BY, int MINW>
@@ -1152,7 +1167,9 @@ hipError_t launch_cfg(const StageArgs<T>& s, int zchunk, int mode, bool at, hipS
     a.gby = (int)gy;
     const size_t dyn = s.force.table ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid(gx * gy * gz), block(Tile<BX, BY>::NT);
-    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T, BX, BY>(MINW);
+    constexpr int MA = fp64_at_cap<T, BX, BY>(at_waves<BX, BY>(MINW));
+    constexpr int MP = fp64_at_cap<T, BX, BY>(pub_at_waves<T, BX, BY>(MA));
+    constexpr int MS = fp64_at_cap<T, BX, BY>(sub_waves<T, BX, BY>(MINW));
     const bool sub = at && s.at_ghost;
     if (s.c_prev != T(0)) {  // an Adams-Bashforth step with a stored register (always publishes)
       if (!s.publish || mode != kModeStep) return hipErrorInvalidValue;
@@ -1356,7 +1373,7 @@ hipError_t launch_fused(const StageArgs<T>& a, int tile, int zchunk, int mode, b
     case 2: return launch_cfg<T, 32, 8, f32 ? 4 : 2>(a, zchunk, mode, at, stream);
     case 3: return launch_cfg<T, 32, 4, f32 ? 2 : 1>(a, zchunk, mode, at, stream);
     case 4: return launch_cfg<T, 64, 4, f32 ? 3 : 2>(a, zchunk, mode, at, stream);
-    case 5: return launch_cfg<T, 16, 8, f32 ? 2 : 1>(a, zchunk, mode, at, stream);
+    case 5: return launch_cfg<T, 16, 8, 2>(a, zchunk, mode, at, stream);
     case 6: return launch_cfg<T, 16, 16, f32 ? 4 : 2>(a, zchunk, mode, at, stream);
     default: return hipErrorInvalidValue;
   }
@@ -1391,7 +1408,9 @@ hipError_t launch_batch_cfg(const void* runs, const uint2* work, int64_t nblk, b
     const size_t dyn = forced ? sizeof(T) * 18 * BX * BY : 0;
     const dim3 grid((unsigned)nblk), block(Tile<BX, BY>::NT);
     const FArgs<T>* r = (const FArgs<T>*)runs;
-    constexpr int MA = at_waves<BX, BY>(MINW), MP = pub_at_waves<T, BX, BY>(MA), MS = sub_waves<T, BX, BY>(MINW);
+    constexpr int MA = fp64_at_cap<T, BX, BY>(at_waves<BX, BY>(MINW));
+    constexpr int MP = fp64_at_cap<T, BX, BY>(pub_at_waves<T, BX, BY>(MA));
+    constexpr int MS = fp64_at_cap<T, BX, BY>(sub_waves<T, BX, BY>(MINW));
     if (at == 0) {
       if (publish)
         hipLaunchKernelGGL((k_stage_batch<T, BX, BY, MINW, true, false, false>), grid, block, dyn, stream, r, work, mode);
@@ -1429,7 +1448,7 @@ hipError_t launch_fused_batch(const void* runs, const uint2* work, int64_t nblk,
     case 2: return launch_batch_cfg<T, 32, 8, f32 ? 4 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
     case 3: return launch_batch_cfg<T, 32, 4, f32 ? 2 : 1>(runs, work, nblk, forced, publish, at, mode, stream);
     case 4: return launch_batch_cfg<T, 64, 4, f32 ? 3 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
-    case 5: return launch_batch_cfg<T, 16, 8, f32 ? 2 : 1>(runs, work, nblk, forced, publish, at, mode, stream);
+    case 5: return launch_batch_cfg<T, 16, 8, 2>(runs, work, nblk, forced, publish, at, mode, stream);
     case 6: return launch_batch_cfg<T, 16, 16, f32 ? 4 : 2>(runs, work, nblk, forced, publish, at, mode, stream);
     default: return hipErrorInvalidValue;
   }
