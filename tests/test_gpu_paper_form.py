@@ -70,18 +70,22 @@ def compare_stats(gs, os_, tol):
     assert gs["step"] == os_["step"] and gs["nonfinite"] == 0
 
 
-@pytest.mark.parametrize("visc", [0, 1])
-def test_paper_rhs_random_delays_history_levels(visc):
-    """RHS on a ragged grid (40 x 20 x 10 on 4 x 2 x 2 PEs of 10 x 10 x 5), six supplied levels and
-    random delays 0..3 on every face at the current step: every ghost level, both viscosity laws."""
-    n, p, nlev = (40, 20, 10), (4, 2, 2), 6
+@pytest.mark.parametrize("visc,n,p,seed", [(0, (40, 20, 10), (4, 2, 2), 3), (1, (40, 20, 10), (4, 2, 2), 4),
+                                            (0, (32, 48, 20), (2, 3, 2), 31), (1, (32, 48, 20), (2, 3, 2), 32)])
+def test_paper_rhs_random_delays_history_levels(visc, n, p, seed):
+    """RHS with six supplied levels and random delays 0..3 on every face at the current step: every
+    ghost level, both viscosity laws.  A ragged grid (40 x 20 x 10 on 4 x 2 x 2 PEs of 10 x 10 x 5)
+    runs the point-per-thread kernels; PEs of 16 x 16 x 10 run the LDS tiles, whose halos then
+    hold the extrapolated values of delayed x and y faces."""
+    nlev = 6
     say(f"case paper-form rhs {n} on {p}, visc {visc}")
     dt = 2e-3
     law, param = ("power", (19, 25)) if visc == 0 else ("sutherland", (2, 5))
     q = history(n, nlev, dt, law, param)
     g, o = pair(n, p, dt, 0.05, visc=visc, suth=0.4)
-    tab = np.zeros((nlev + 1, 16, 6), dtype=np.int8)
-    tab[nlev - 1] = np.random.default_rng(3 + visc).integers(0, 4, size=(16, 6))
+    npe = p[0] * p[1] * p[2]
+    tab = np.zeros((nlev + 1, npe, 6), dtype=np.int8)
+    tab[nlev - 1] = np.random.default_rng(seed).integers(0, 4, size=(npe, 6))
     for s in (g, o):
         s.init_field(q, nlev)
     g.set_delay_schedule(atns.EXPLICIT, table=tab)
