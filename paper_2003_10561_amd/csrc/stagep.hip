@@ -66,10 +66,21 @@ __device__ __forceinline__ T sel(bool c, T x, T y) {
   return c ? x : y;
 }
 
+// 1 / x: the hardware reciprocal in FP32 (1 ulp, as the fourth-order stage kernel uses), a
+// correctly rounded division in FP64.
+template <typename T>
+__device__ __forceinline__ T prcp(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float prcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
 // u, v, w, T, p, then for direction d: m_d, m_i m_d / rho (i = 0..2), rho e m_d / rho.
 template <typename T>
 __device__ __forceinline__ void derive(const PA<T>& a, const T q[5], int d, T v[10]) {
-  const T rinv = T(1) / q[0];
+  const T rinv = prcp<T>(q[0]);
   v[0] = q[1] * rinv;
   v[1] = q[2] * rinv;
   v[2] = q[3] * rinv;
@@ -123,8 +134,9 @@ template <typename T>
 __device__ __forceinline__ T viscosity(const PA<T>& a, T temp, T* dmu) {
   if (a.visc == 1) {
     const T t = temp * a.inv_tref;
-    const T mu = a.mu_ref * t * sqrt(t) * (T(1) / a.inv_tref + a.suth_s) / (temp + a.suth_s);
-    *dmu = mu * (T(1.5) / temp - T(1) / (temp + a.suth_s));
+    const T rts = prcp<T>(temp + a.suth_s);
+    const T mu = a.mu_ref * t * sqrt(t) * (T(1) / a.inv_tref + a.suth_s) * rts;
+    *dmu = mu * (T(1.5) * prcp<T>(temp) - rts);
     return mu;
   }
   const T mu = a.mu_ref * pow(temp * a.inv_tref, a.mu_exp);
@@ -565,14 +577,14 @@ __device__ __forceinline__ int halo_k(const int (*s_kd)[6], int zl, const Halo& 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void kp_grad_tile(PA<T> a, int publish) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void kp_grad_tile(PA<T> a, int publish) {
   constexpr int LW = kTB + 2 * kTH;
   __shared__ T s_u[4][LW][LW];  // u, v, w, T of the plane, tile and x / y halos (corners unused)
   __shared__ int s_kd[kMaxZPe][6];
   const TBrick b = tbrick(a);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTB + tx;
   const int x = b.x0 + tx, y = b.y0 + ty;
-  const int nz = a.n[2], ez = a.e[2], zp0 = b.z0 / ez;
+  const int nz = a.n[2], ez = a.e[2];
   const HaloRole hr = halo_role(tid);
   const Halo h = halo_of(a, hr.d, hr.on ? tid - 4 * kTB * hr.d : 0, b.x0, b.y0);
   load_delays(a, b, s_kd, tid);
@@ -612,14 +624,13 @@ __global__ __launch_bounds__(256) void kp_grad_tile(PA<T> a, int publish) {
   T qn[5];
   load_q(a, x, y, wrapi(b.z0 + 3, nz), qn);
   if (hr.on && b.z0 + 1 < b.z1) {
-    const int zz = b.z0 + 1;
-    hk = halo_k(s_kd, zz / ez - zp0, h);
-    fetch_raw(a, h.pt[0], h.pt[1], zz, hr.d, hk, hw);
+    hk = halo_k(s_kd, (b.z0 % ez) + 1 >= ez ? 1 : 0, h);
+    fetch_raw(a, h.pt[0], h.pt[1], b.z0 + 1, hr.d, hk, hw);
   }
 
+  int lz = b.z0 % ez, zl = 0;  // plane z: its index in its z-PE, that z-PE within the chunk
   for (int z = b.z0; z < b.z1; ++z) {
     __syncthreads();
-    const int zl = z / ez - zp0, lz = z % ez;
     const uint32_t i = ((uint32_t)z * a.n[1] + y) * a.n[0] + x;
     const T c1[4] = {T(1), T(-8), T(8), T(-1)};
     const int off[4] = {-2, -1, 1, 2};
@@ -649,11 +660,11 @@ __global__ __launch_bounds__(256) void kp_grad_tile(PA<T> a, int publish) {
       }
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 4; ++c) {  // streamed out (read by the next launch)
       const uint32_t g0 = (uint32_t)(c < 3 ? 3 * c : 9);
-      a.grad[(g0 + 0) * a.N + i] = gx[c] * a.i12h[0];
-      a.grad[(g0 + 1) * a.N + i] = gy[c] * a.i12h[1];
-      a.grad[(g0 + 2) * a.N + i] = gz[c] * a.i12h[2];
+      __builtin_nontemporal_store(gx[c] * a.i12h[0], a.grad + (g0 + 0) * a.N + i);
+      __builtin_nontemporal_store(gy[c] * a.i12h[1], a.grad + (g0 + 1) * a.N + i);
+      __builtin_nontemporal_store(gz[c] * a.i12h[2], a.grad + (g0 + 2) * a.N + i);
     }
     __syncthreads();
     if (z + 1 < b.z1) {  // uniform
@@ -686,10 +697,13 @@ __global__ __launch_bounds__(256) void kp_grad_tile(PA<T> a, int publish) {
       // fetch for plane z + 2: the column's plane z + 4 and the halo points
       load_q(a, x, y, wrapi(z + 4, nz), qn);
       if (hr.on && z + 2 < b.z1) {
-        const int zz = z + 2;
-        hk = halo_k(s_kd, zz / ez - zp0, h);
-        fetch_raw(a, h.pt[0], h.pt[1], zz, hr.d, hk, hw);
+        hk = halo_k(s_kd, zl + (lz + 2 >= ez ? 1 : 0), h);
+        fetch_raw(a, h.pt[0], h.pt[1], z + 2, hr.d, hk, hw);
       }
+    }
+    if (++lz == ez) {
+      lz = 0;
+      ++zl;
     }
   }
 }
@@ -713,6 +727,24 @@ __device__ __forceinline__ T line_d1(F at, int l, int e, T i12h) {
   return s * i12h;
 }
 
+// The five-point window of the PE-local first derivative at local index l of a PE of edge e (the
+// stencils of pe_d1): its case (0 central, 1 l = 0, 2 l = 1, 3 l = e - 2, 4 l = e - 1), whose
+// row of kLineCoef holds the numerators, and its first offset.
+__device__ __forceinline__ int line_case(int l, int e) {
+  return l >= 2 && l <= e - 3 ? 0 : (l == 0 ? 1 : (l == 1 ? 2 : (l == e - 2 ? 3 : 4)));
+}
+__device__ __forceinline__ int line_first(int cs) {
+  return cs == 0 ? -2 : (cs == 1 ? 0 : (cs == 2 ? -1 : (cs == 3 ? -3 : -4)));
+}
+__device__ __forceinline__ double line_coef(int cs, int j) {
+  constexpr double k[5][5] = {{1, -8, 0, 8, -1},
+                              {-25, 48, -36, 16, -3},
+                              {-3, -10, 18, -6, 1},
+                              {-1, 6, -18, 10, 3},
+                              {3, -16, 36, -48, 25}};
+  return k[cs][j];
+}
+
 // Gradient components whose PE-local lines the mixed derivatives take along x (dv/dy, dw/dz,
 // du/dy, du/dz), along y (dv/dx, du/dx, dw/dz, dw/dy) and along z (du/dx, dv/dy, dw/dx, dw/dy).
 __host__ __device__ constexpr int kGx(int c) { return c == 0 ? 4 : (c == 1 ? 8 : (c == 2 ? 1 : 2)); }
@@ -722,7 +754,7 @@ __host__ __device__ constexpr int kGz(int c) { return c == 0 ? 0 : (c == 1 ? 4 :
 __host__ __device__ constexpr int kGo(int c) { return c < 6 ? c : 8; }
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void kp_rhs_tile(PA<T> a) {
   constexpr int LW = kTB + 2 * kTH, GW = kTB + 2 * kTG, NP = kTB * kTB;
   __shared__ T s_u[5][LW][LW];         // u, v, w, T, p: tile and x / y halos (corners unused)
   __shared__ T s_fx[5][kTB][LW];       // m_x, m_i u, rho e u on the tile rows with the x halo
@@ -731,11 +763,15 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
   __shared__ T s_gy[4][GW][kTB];       // gradients kGy on the tile columns, y halo 4
   __shared__ T s_gz[kTRing][4][NP];    // gradients kGz of planes z - 4 .. z + 4 (slot by plane)
   __shared__ int s_kd[kMaxZPe][6];
+  __shared__ T s_lc[5][5];             // line stencil numerators by case
   const TBrick b = tbrick(a);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTB + tx;
   const int x = b.x0 + tx, y = b.y0 + ty;
-  const int lx = x % a.e[0], ly = y % a.e[1];
-  const int nz = a.n[2], ez = a.e[2], zp0 = b.z0 / ez;
+  // this thread's PE-local x and y line windows (fixed for the march): case and first offset
+  const int cxs = line_case(x % a.e[0], a.e[0]), cys = line_case(y % a.e[1], a.e[1]);
+  const int ox = line_first(cxs), oy = line_first(cys);
+  if (tid < 25) s_lc[tid / 5][tid % 5] = (T)line_coef(tid / 5, tid % 5);
+  const int nz = a.n[2], ez = a.e[2];
   const bool need_dq = a.rk_a != T(0) || a.c_prev != T(0);
   const HaloRole hr = halo_role(tid);
   const Halo h = halo_of(a, hr.d, hr.on ? tid - 4 * kTB * hr.d : 0, b.x0, b.y0);
@@ -744,11 +780,16 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
   const int gl = gj < 4 ? gj : kTB + gj;
   const int ghx = gd == 0 ? wrapi(b.x0 + (gj < 4 ? gj - 4 : kTB + gj - 4), a.n[0]) : b.x0 + galong;
   const int ghy = gd == 0 ? b.y0 + galong : wrapi(b.y0 + (gj < 4 ? gj - 4 : kTB + gj - 4), a.n[1]);
-  auto gidx = [&](int xx, int yy, int zz) {  // zz may lie up to 6 planes outside the grid
-    const int zw = (zz % nz + nz) % nz;
+  auto gidx = [&](int xx, int yy, int zz) {  // zz may lie a few planes outside the grid
+    int zw = zz;
+    while (zw < 0) zw += nz;
+    while (zw >= nz) zw -= nz;
     return ((uint32_t)zw * a.n[1] + yy) * a.n[0] + xx;
   };
-  auto ring_slot = [&](int zz) { return (zz - b.z0 + kTG) % kTRing; };  // zz >= z0 - 4
+  auto ring_add = [](int sl, int o) {  // ring slot o planes from slot sl, |o| < kTRing
+    const int t = sl + o;
+    return t < 0 ? t + kTRing : (t >= kTRing ? t - kTRing : t);
+  };
   load_delays(a, b, s_kd, tid);
 
   // plane-z registers and the fetches for the next plane
@@ -764,7 +805,7 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
   for (int zz = b.z0 - kTG; zz <= b.z0 + kTG; ++zz) {
     const uint32_t iz = gidx(x, y, zz);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) s_gz[ring_slot(zz)][c][tid] = a.grad[(uint32_t)kGz(c) * a.N + iz];
+    for (int c = 0; c < 4; ++c) s_gz[zz - b.z0 + kTG][c][tid] = a.grad[(uint32_t)kGz(c) * a.N + iz];
   }
   {
     const uint32_t i0 = gidx(x, y, b.z0), ih = gidx(ghx, ghy, b.z0);
@@ -820,7 +861,7 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
     }
   };
   // Issues the loads for plane zz (the column's plane zz + 2, the ring plane zz + 4).
-  auto fetch_plane = [&](int zz) {
+  auto fetch_plane = [&](int zz, int zzl) {  // zzl: the z-PE of plane zz within the chunk
     load_q(a, x, y, wrapi(zz + 2, nz), qn);
     const uint32_t io = gidx(x, y, zz), ih = gidx(ghx, ghy, zz), ir = gidx(x, y, zz + kTG);
 #pragma unroll
@@ -832,19 +873,20 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) gTn[c] = a.grad[(uint32_t)(9 + c) * a.N + io];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) dqn[c] = need_dq ? a.dq[(uint32_t)c * a.N + io] : T(0);
+    for (int c = 0; c < 5; ++c) dqn[c] = need_dq ? __builtin_nontemporal_load(a.dq + (uint32_t)c * a.N + io) : T(0);
     if (hr.on && zz < b.z1) {
-      hk = halo_k(s_kd, zz / ez - zp0, h);
+      hk = halo_k(s_kd, zzl, h);
       fetch_raw(a, h.pt[0], h.pt[1], zz, hr.d, hk, hw);
     }
   };
   stage_plane();
-  fetch_plane(b.z0 + 1);
+  const int lz0 = b.z0 % ez;
+  fetch_plane(b.z0 + 1, lz0 + 1 >= ez ? 1 : 0);
 
   double tsum[5] = {0, 0, 0, 0, 0};
+  int lz = lz0, zl = 0, s0 = kTG;  // plane z: its index in its z-PE, that z-PE, its ring slot
   for (int z = b.z0; z < b.z1; ++z) {
     __syncthreads();
-    const int zl = z / ez - zp0, lz = z % ez;
     const uint32_t i = ((uint32_t)z * a.n[1] + y) * a.n[0] + x;
     T vc[10];
     derive(a, wq[2], 0, vc);
@@ -909,12 +951,26 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
     // mixed derivatives: d/dx_c du_k/dx_k as the average of the PE-local derivative along x_c of
     // du_k/dx_k and along x_k of du_k/dx_c (k != c)
     T dx[4], dy[4], dzl[4];
-    const int s0 = ring_slot(z);
+    {
+      T kx[5], ky[5];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      dx[c] = line_d1<T>([&](int o) { return s_gx[c][ty][tx + kTG + o]; }, lx, a.e[0], a.i12h[0]);
-      dy[c] = line_d1<T>([&](int o) { return s_gy[c][ty + kTG + o][tx]; }, ly, a.e[1], a.i12h[1]);
-      dzl[c] = line_d1<T>([&](int o) { return s_gz[(s0 + o + kTRing) % kTRing][c][tid]; }, lz, ez, a.i12h[2]);
+      for (int j = 0; j < 5; ++j) {
+        kx[j] = s_lc[cxs][j];
+        ky[j] = s_lc[cys][j];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        // x and y: the thread's window, branch-free; z: uniform cases
+        T sx = kx[0] * s_gx[c][ty][tx + kTG + ox], sy = ky[0] * s_gy[c][ty + kTG + oy][tx];
+#pragma unroll
+        for (int j = 1; j < 5; ++j) {
+          sx += kx[j] * s_gx[c][ty][tx + kTG + ox + j];
+          sy += ky[j] * s_gy[c][ty + kTG + oy + j][tx];
+        }
+        dx[c] = sx * a.i12h[0];
+        dy[c] = sy * a.i12h[1];
+        dzl[c] = line_d1<T>([&](int o) { return s_gz[ring_add(s0, o)][c][tid]; }, lz, ez, a.i12h[2]);
+      }
     }
     // dx: G4 G8 G1 G2; dy: G3 G0 G8 G5; dzl: G0 G4 G6 G7
     T mixed[3];
@@ -938,15 +994,15 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
     // the update (or the RHS alone), with dQ of this plane from registers
     if (a.mode == kModeRhsH) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) a.rhs_out[(uint32_t)c * a.N + i] = rhs[c];
+      for (int c = 0; c < 5; ++c) __builtin_nontemporal_store(rhs[c], a.rhs_out + (uint32_t)c * a.N + i);
     } else {
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         const T prev = dqc[c];
         const T dqv = a.rk_a * prev + a.dt * rhs[c];
         const T inc = a.rk_b * dqv + a.c_prev * prev;
-        if (a.store_dq) a.dq[(uint32_t)c * a.N + i] = dqv;
-        a.q_out[(uint32_t)c * a.N + i] = wq[2][c] + inc;
+        if (a.store_dq) __builtin_nontemporal_store(dqv, a.dq + (uint32_t)c * a.N + i);
+        __builtin_nontemporal_store(wq[2][c] + inc, a.q_out + (uint32_t)c * a.N + i);
         tsum[c] += a.c_prev != T(0) ? (double)inc : (double)dqv;
       }
     }
@@ -964,9 +1020,14 @@ __global__ __launch_bounds__(256, 2) void kp_rhs_tile(PA<T> a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) gT[c] = gTn[c];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) s_gz[ring_slot(z + 1 + kTG)][c][tid] = grn[c];
+      for (int c = 0; c < 4; ++c) s_gz[ring_add(s0, kTG + 1)][c][tid] = grn[c];  // plane z + 5
       stage_plane();
-      fetch_plane(z + 2);
+      fetch_plane(z + 2, zl + (lz + 2 >= ez ? 1 : 0));
+    }
+    s0 = ring_add(s0, 1);
+    if (++lz == ez) {
+      lz = 0;
+      ++zl;
     }
   }
   if (a.mode != kModeStepH) return;  // uniform across the grid
