@@ -254,7 +254,9 @@ def batched_workload(torch, atns, W, steps, warmup, cache):
     b.close()
     del sims
     torch.cuda.empty_cache()
+    ref = same_pe_single_run(torch, atns, W)
     return {"value": pts * steps / (ms * 1e-3), "unit": "grid-pt-steps/s", "runs": len(specs), "points": pts,
+            "same_pe_single_run": ref, "batched_over_same_pe_single": pts * steps / (ms * 1e-3) / ref["value"],
             "steps": steps, "warmup": warmup, "ms_per_step": ms / steps, "tile": tile, "zchunk": zc,
             "tile_delayed": tile_d, "zchunk_delayed": zc_d,
             "autotune_stage_ms": tune_ms, "graph_captures": caps, "graph_replays": reps,
@@ -264,6 +266,30 @@ def batched_workload(torch, atns, W, steps, warmup, cache):
             "nonfinite_runs": int(nonfinite),
             "workload": "64 runs (16 each of 32^3, 64^3, 96^3, 128^3), CAA/SAA L in 1..3, FP32, one batched "
                         "launch per kernel per RK stage from a HIP graph"}
+
+
+def same_pe_single_run(torch, atns, W, n=256, pe=8, steps=10, warmup=3):
+    """The per-point reference for the batched and served workloads, whose members run on PEs of 32^3
+    (16^3 at N = 32): one unforced FP32 run of 256^3 on 8x8x8 PEs of 32^3, CAA L=3 c_r=4, autotuned
+    launch shapes (the 512^3 headline runs on PEs of 64^3, with half the face work per point)."""
+    q = W.make_field(n, 77, 0.3)
+    cfg = atns.Config(n=(n,) * 3, p=(pe,) * 3, dt=W.default_dt(q), mu_ref=W.default_mu(n), max_delay=3,
+                      precision="fp32")
+    sim = atns.Sim(cfg)
+    sim.init_field(q)
+    sim.set_delay_schedule(atns.CAA, L=3, c_r=4, n_steps=warmup + steps + 8)
+    b = atns.Batch("fp32")
+    b.add(sim)
+    b.autotune(None, reps=2)
+    shapes = b.get_stage_tuning()
+    b.remove(sim)
+    b.close()
+    sim.set_stage_tuning(*shapes)
+    ms = time_window(torch, sim, steps, warmup=warmup)
+    sim.close()
+    torch.cuda.empty_cache()
+    return {"value": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps, "launch": list(shapes),
+            "workload": f"one run of {n}^3 on {pe}x{pe}x{pe} PEs of {n // pe}^3, CAA L=3 c_r=4, unforced, FP32"}
 
 
 def served_workload(atns, W, seconds, seed=5, tile=-1, zchunk=64, tile_delayed=-1, zchunk_delayed=64):

@@ -27,6 +27,11 @@ struct at_batch {
   int precision = AT_FP32;
   hipStream_t stream = nullptr;  // caller's stream: table uploads and graph launches
   hipStream_t cap = nullptr;     // private stream, used only to capture graphs
+  // private stream of the AT branch of a stage (the AT sums and the AT launch), forked from and
+  // joined back into the launch stream at every stage, so that the plain and the AT launches of a
+  // stage (disjoint sets of runs) overlap; default priority
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
   std::vector<at_sim*> runs;
   int tile = 1, zchunk = 64;      // launch shape of the stages that read no delayed level
@@ -241,19 +246,28 @@ hipError_t enqueue_chunk(at_batch* b, const ChunkPlan& p, hipStream_t st) {
     for (int stg = 0; stg < 3; ++stg) {
       const void* tab = b->d_buf + p.off_args[0] + (size_t)(bs * 3 + stg) * M * p.argb;
       const void* tabd = b->d_buf + p.off_args[1] + (size_t)(bs * 3 + stg) * M * p.argb;
-      if (stg == 0 && p.views && p.nvw > 0) {  // the AT sums of all three stages of the step
-        hipError_t e = launch_at_sums_batch<T>(tab, vw, p.nvw, kRkC, st);
-        if (e != hipSuccess) return e;
-      }
       // runs that read delayed levels at this step run the AT instantiation (in its own launch
       // shape), the others the plain one (each leaves the other's launch at once); both are
       // launched at every stage of a batch with any delayed schedule, so that a chunk's graph
-      // depends only on membership, launch shapes and length
-      hipError_t e = launch_fused_batch<T>(tab, sw, p.nsw[0], b->tile, forced, stg == 0, 0, kModeStepH, st);
+      // depends only on membership, launch shapes and length.  The AT branch (with the AT sums of
+      // the step at stage 1) runs on the side stream, concurrently with the plain launch: a run's
+      // stage touches only its own buffers, and the join orders every run's stages.
+      hipError_t e = hipSuccess;
+      if (p.views) {
+        if ((e = hipEventRecord(b->ev_fork, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(b->side, b->ev_fork, 0)) != hipSuccess) return e;
+        if (stg == 0 && p.nvw > 0) {  // the AT sums of all three stages of the step
+          e = launch_at_sums_batch<T>(tab, vw, p.nvw, kRkC, b->side);
+          if (e != hipSuccess) return e;
+        }
+        e = launch_fused_batch<T>(tabd, swd, p.nsw[1], b->tile_d, forced, stg == 0, p.at_kinds, kModeStepH, b->side);
+        if (e != hipSuccess) return e;
+      }
+      e = launch_fused_batch<T>(tab, sw, p.nsw[0], b->tile, forced, stg == 0, 0, kModeStepH, st);
       if (e != hipSuccess) return e;
       if (p.views) {
-        e = launch_fused_batch<T>(tabd, swd, p.nsw[1], b->tile_d, forced, stg == 0, p.at_kinds, kModeStepH, st);
-        if (e != hipSuccess) return e;
+        if ((e = hipEventRecord(b->ev_join, b->side)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, b->ev_join, 0)) != hipSuccess) return e;
       }
     }
   }
@@ -574,6 +588,9 @@ int at_batch_create(int32_t precision, void* stream, at_batch** out) {
   b->tile = b->tile_d = fused_lds_bytes(1, word_of(precision), false) <= kLdsBytes ? 1 : 5;
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&b->h_done[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     at_batch_destroy(b);
@@ -704,6 +721,12 @@ int at_batch_destroy(at_batch* b) {
     if (b->h_buf[i]) (void)hipHostFree(b->h_buf[i]);
     if (b->h_done[i]) (void)hipEventDestroy(b->h_done[i]);
   }
+  if (b->side) {
+    (void)hipStreamSynchronize(b->side);
+    (void)hipStreamDestroy(b->side);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
   return AT_OK;
