@@ -21,8 +21,11 @@
  *   - The device workspace and the HIP stream belong to the caller, who keeps both alive until
  *     at_destroy; the library never frees them.  The library itself allocates (hipMalloc) only the
  *     delay table, the forcing table and a small staging buffer, and frees them in at_destroy.
- *   - All device work is enqueued on the caller's stream; calls returning host data
- *     (at_stats, at_get_field) synchronise that stream.  One host thread per handle.
+ *   - All device work is ordered on the caller's stream; calls returning host data
+ *     (at_stats, at_get_field) synchronise that stream.  Batches fork the AT launches of each
+ *     stage onto a stream of their own and join it back into the caller's stream within the
+ *     call, so that when a call's work on the caller's stream has completed, all of it has.  One
+ *     host thread per handle.
  *   - NaN / Inf in the state is reported through at_stats.nonfinite, not as an error.
  */
 #ifndef ATNS_H
