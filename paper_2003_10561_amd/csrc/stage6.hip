@@ -283,7 +283,8 @@ __global__ __launch_bounds__(256) void k6_gradflux(A6<T> a) {
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int c = 0; c < 5; ++c) a.flux[(uint32_t)(d * 5 + c) * a.N + i] = F[d][c];
+      for (int c = 0; c < 5; ++c)  // streamed out: read by the next launch, far beyond the caches
+        __builtin_nontemporal_store(F[d][c], a.flux + (uint32_t)(d * 5 + c) * a.N + i);
     if (a.publish) {
       const int lxe = X - pxl, lye = Y - pyl, lze = zc - z0;
       const bool on[3] = {lxe < kM6 || lxe >= a.ex - kM6, lye < kM6 || lye >= a.ey - kM6,
@@ -381,16 +382,17 @@ __global__ __launch_bounds__(256) void k6_divupdate(A6<T> a) {
     }
     if (a.mode == kModeRhsH) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) a.rhs_out[(uint32_t)c * a.N + i] = rhs[c];
+      for (int c = 0; c < 5; ++c) __builtin_nontemporal_store(rhs[c], a.rhs_out + (uint32_t)c * a.N + i);
     } else {
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         const T qv = a.q[(uint32_t)c * a.N + i];
-        const T prev = (a.rk_a != T(0) || a.c_prev != T(0)) ? a.dq[(uint32_t)c * a.N + i] : T(0);
+        const T prev = (a.rk_a != T(0) || a.c_prev != T(0)) ? __builtin_nontemporal_load(a.dq + (uint32_t)c * a.N + i)
+                                                             : T(0);
         const T d = a.rk_a * prev + a.dt * rhs[c];
         const T inc = a.rk_b * d + a.c_prev * prev;
-        if (a.store_dq) a.dq[(uint32_t)c * a.N + i] = d;
-        a.q_out[(uint32_t)c * a.N + i] = qv + inc;
+        if (a.store_dq) __builtin_nontemporal_store(d, a.dq + (uint32_t)c * a.N + i);
+        __builtin_nontemporal_store(qv + inc, a.q_out + (uint32_t)c * a.N + i);
         tsum[c] += a.c_prev != T(0) ? (double)inc : (double)d;
       }
     }
