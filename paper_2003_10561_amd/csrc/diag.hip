@@ -182,6 +182,18 @@ __device__ void fft_lines(double2* buf, const Axis& a, int nlines, int ls, int e
 }
 
 // Twiddle table exp(-2 pi i e / ntw), e = 0 .. ntw-1 (sincospi of an exact argument).
+// Streamed accesses of the pass buffers (each written once by one pass and read once by the
+// next, far beyond the caches at the sizes these passes serve).
+typedef double dvec2 __attribute__((ext_vector_type(2)));  // 16 bytes, the layout of double2
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  const dvec2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<dvec2*>(p));
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const dvec2 w = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+  return make_double2(w.x, w.y);
+}
+
 __global__ void k_twiddle(double2* tw, int ntw) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ntw) return;
@@ -291,7 +303,7 @@ __global__ __launch_bounds__(256) void k_diag_pts(const T* __restrict__ q, int n
     for (int z = z0; z < z1; ++z) {
       double g, e, o, p;
       point_values<T, M>(q, nx, ny, nz, N, x, y, z, ph, g, e, o, p);
-      eo[((int64_t)z * ny + y) * nx + x] = make_double2(e, o);
+      st_stream(&eo[((int64_t)z * ny + y) * nx + x], make_double2(e, o));
       const double g2 = g * g;
       s[0] += g2;
       s[1] += g2 * g;
@@ -334,7 +346,7 @@ __global__ __launch_bounds__(256) void k_diag_hist(const double2* __restrict__ e
     for (int c = 0; c < kHistPts; ++c) {
       const int64_t i = i0 + c * kThreads + threadIdx.x;
       if (i < N) {
-        const double2 v = eo[i];
+        const double2 v = ld_stream(&eo[i]);
         if (do_e) atomicAdd(&hs[pdf_bin(v.x / me, scale_e, nbins)], 1u);
         if (do_o) atomicAdd(&hs[nbins + 1 + pdf_bin(v.y / mo, scale_o, nbins)], 1u);
       }
@@ -435,8 +447,8 @@ __global__ __launch_bounds__(256) void k_fft_x(const T* __restrict__ q, int nx, 
     const double2 B = make_double2(0.5 * (zk.y + zm.y), -0.5 * (zk.x - zm.x));
     const int f = 2 * (rl & 1);
     const int64_t o = (row0 + (rl >> 1)) * px + kx;
-    S[f * fstride + o] = A;
-    S[(f + 1) * fstride + o] = B;
+    st_stream(&S[f * fstride + o], A);
+    st_stream(&S[(f + 1) * fstride + o], B);
   }
 }
 
@@ -450,13 +462,13 @@ __global__ __launch_bounds__(kThreadsYZ) void k_fft_y(double2* __restrict__ S, i
   double2* base = S + f * fstride + (int64_t)z * ny * px + kx0;
   for (int t = threadIdx.x; t < ny * bx; t += kThreadsYZ) {
     const int y = t / bx, l = t - y * bx;
-    lds[t] = l < nv ? base[(int64_t)y * px + l] : make_double2(0.0, 0.0);
+    lds[t] = l < nv ? ld_stream(&base[(int64_t)y * px + l]) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   fft_lines<kThreadsYZ, false>(lds, ay, bx, 1, bx, tw, true);
   for (int t = threadIdx.x; t < ny * bx; t += kThreadsYZ) {
     const int y = t / bx, l = t - y * bx;
-    if (l < nv) base[(int64_t)y * px + l] = lds[t];
+    if (l < nv) st_stream(&base[(int64_t)y * px + l], lds[t]);
   }
 }
 
@@ -495,7 +507,7 @@ __global__ __launch_bounds__(kThreadsYZ) void k_fft_z_shell(const double2* __res
   const int64_t zs = (int64_t)ny * px;
   for (int t = threadIdx.x; t < nz * bx; t += kThreadsYZ) {
     const int z = t / bx, l = t - z * bx;
-    lds[t] = l < nv ? base[z * zs + l] : make_double2(0.0, 0.0);
+    lds[t] = l < nv ? ld_stream(&base[z * zs + l]) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   fft_lines<kThreadsYZ, false>(lds, az, bx, 1, bx, tw, true);
