@@ -62,7 +62,9 @@ def test_noalloc_stats_match_at_stats_two_calls(precision):
 def test_noalloc_rejects_grid_beyond_scratch():
     cfg = atns.Config(n=(320, 320, 320), p=(1, 1, 1), dt=1e-3, mu_ref=1e-3, max_delay=0)
     out = torch.zeros(atns.STATS_RECORD_BYTES, dtype=torch.uint8, device="cuda")
-    q = torch.zeros(8, dtype=torch.float64, device="cuda")  # never read: the call is rejected first
+    # a zero field of the full size (1.3 GB), so that were the call not rejected, the statistics
+    # kernel would still read only memory of the field (the test would fail, not fault)
+    q = torch.zeros((5,) + tuple(reversed(cfg.n)), dtype=torch.float64, device="cuda")  # [5][nz][ny][nx]
     with pytest.raises(atns.AtError) as e:
         atns.field_stats_noalloc(cfg, q.data_ptr(), out.data_ptr())
     assert e.value.rc == atns.AT_E_INVAL
