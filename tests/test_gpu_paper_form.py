@@ -71,12 +71,14 @@ def compare_stats(gs, os_, tol):
 
 
 @pytest.mark.parametrize("visc,n,p,seed", [(0, (40, 20, 10), (4, 2, 2), 3), (1, (40, 20, 10), (4, 2, 2), 4),
-                                            (0, (32, 48, 20), (2, 3, 2), 31), (1, (32, 48, 20), (2, 3, 2), 32)])
+                                            (0, (32, 48, 20), (2, 3, 2), 31), (1, (32, 48, 20), (2, 3, 2), 32),
+                                            (1, (32, 16, 80), (2, 1, 8), 33)])
 def test_paper_rhs_random_delays_history_levels(visc, n, p, seed):
     """RHS with six supplied levels and random delays 0..3 on every face at the current step: every
     ghost level, both viscosity laws.  A ragged grid (40 x 20 x 10 on 4 x 2 x 2 PEs of 10 x 10 x 5)
     runs the point-per-thread kernels; PEs of 16 x 16 x 10 run the LDS tiles, whose halos then
-    hold the extrapolated values of delayed x and y faces."""
+    hold the extrapolated values of delayed x and y faces; at 80 planes the tiles' second z chunk
+    (64 planes each) starts inside a PE, with six z-PEs in the first."""
     nlev = 6
     say(f"case paper-form rhs {n} on {p}, visc {visc}")
     dt = 2e-3
