@@ -230,18 +230,15 @@ __device__ __forceinline__ void add5(T acc[kNQ], int c, T val) {
 }
 
 // Per-column window of the z march: u, v, w, T of planes zc-2 .. zc+2 (index j = 0 .. 4) and rho,
-// E of plane zc, for the current plane zc; push() brings in plane zc + 3 and advances zc.  FP32
-// keeps it in registers (shifted one plane per push), and so do the FP64 stages without AT
-// stencils (they fit 2 waves per SIMD without spills, and the LDS freed lets 2 workgroups share a
-// CU); the FP64 AT stages keep it in a thread-private LDS ring (slot z mod 5, z mod 3), since in
-// registers they would spill.
-template <typename T, int NCOL, bool REG>
-struct ZWin;
-
-template <typename T, int NCOL>
-struct ZWin<T, NCOL, true> {
+// E of plane zc, for the current plane zc; push() brings in plane zc + 3 and advances zc.  It lives
+// in registers (shifted one plane per push) in every instantiation: the FP64 AT ones of 4-wave
+// workgroups run one wave per SIMD, whose budget (VGPRs plus AGPRs) holds it without scratch; those
+// of larger workgroups spill part of their state to scratch, but keep the arithmetic, and so the
+// rounding, of the others.
+template <typename T>
+struct ZWin {
   T w[4][5], re[2][3];
-  __device__ __forceinline__ void init(T (*)[NCOL], int, int) {
+  __device__ __forceinline__ void init() {
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -277,39 +274,6 @@ struct ZWin<T, NCOL, true> {
   }
 };
 
-template <typename T, int NCOL>
-struct ZWin<T, NCOL, false> {
-  T (*s)[NCOL];  // [26][NCOL]: 5 c + slot for u, v, w, T; 20 + 3 (c - 4) + slot for rho, E
-  int wc, sb, sr;
-  __device__ __forceinline__ int s5(int j) const { return sb + j >= 5 ? sb + j - 5 : sb + j; }
-  __device__ __forceinline__ int s3(int j) const { return sr + j >= 3 ? sr + j - 3 : sr + j; }
-  __device__ __forceinline__ void init(T (*lds)[NCOL], int col, int zc) {
-    s = lds;
-    wc = col;
-    sb = pmod(zc - 2, 5);
-    sr = pmod(zc, 3);
-  }
-  __device__ __forceinline__ void fill(int j, T u, T v, T ww, T t) {
-    s[0 + s5(j)][wc] = u;
-    s[5 + s5(j)][wc] = v;
-    s[10 + s5(j)][wc] = ww;
-    s[15 + s5(j)][wc] = t;
-  }
-  __device__ __forceinline__ void fill_re(int j, T r, T e) {
-    s[20 + s3(j)][wc] = r;
-    s[23 + s3(j)][wc] = e;
-  }
-  __device__ __forceinline__ T get(int c, int j) const { return s[5 * c + s5(j)][wc]; }
-  __device__ __forceinline__ T rho() const { return s[20 + sr][wc]; }
-  __device__ __forceinline__ T E() const { return s[23 + sr][wc]; }
-  __device__ __forceinline__ void push(T u, T v, T ww, T t, T r, T e) {
-    fill(0, u, v, ww, t);  // plane zc + 3 takes the slot of plane zc - 2
-    fill_re(0, r, e);      // and of plane zc
-    sb = s5(1);
-    sr = s3(1);
-  }
-};
-
 // window element of component c (0 u, 1 v, 2 w, 3 T) at plane index j (plane zc - 2 + j)
 #define WIN(c, j) zw.get(c, j)
 
@@ -333,8 +297,6 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   __shared__ T s_fx[2][5][BY][BX + 4];   // F_x on the tile rows, x halo 2
   __shared__ T s_fy[2][5][BY + 4][BX];   // F_y on the tile columns, y halo 2
   __shared__ double s_tsum[kNQ][TL::NOWN];  // FP64 running sums of dQ per tile column
-  constexpr bool kRegWin = sizeof(T) == 4 || !AT;
-  __shared__ T s_win[kRegWin ? 1 : 26][kRegWin ? 1 : TL::NCOL];
   extern __shared__ unsigned char s_dyn[];  // forcing coefficients when forced
   T* s_force = reinterpret_cast<T*>(s_dyn);
 
@@ -473,8 +435,8 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
   for (int j = 0; j < 5; ++j)
 #pragma unroll
     for (int c = 0; c < kNQ; ++c) acc[j][c] = T(0);
-  ZWin<T, kRegWin ? 1 : TL::NCOL, kRegWin> zw;
-  zw.init(s_win, column ? tid : 0, z0 - 2);
+  ZWin<T> zw;
+  zw.init();
   if (column) {
     // planes z0-4 .. z0-1 into the window; z0 arrives through `raw`
 #pragma unroll
@@ -967,7 +929,7 @@ __device__ __forceinline__ void stage_body(const FArgs<T>& a, const int mode, co
       if (column) {
         T r_, u_, v_, w_, e_ = raw[4];
         prim_of<T>(raw, inv_cv, r_, u_, v_, w_, t_);
-        if constexpr (kRegWin && sizeof(T) == 4) {
+        if constexpr (sizeof(T) == 4) {
           r_ = own_copy(r_);
           e_ = own_copy(e_);
         }
@@ -1132,24 +1094,25 @@ constexpr int sub_waves(int minw) {
 }
 
 // Static LDS of the stage kernel (must fit a compute unit: 160 KiB on gfx950); the halo AT-sum
-// slots of the aligned-tile instantiations, and the FP64 LDS window of the AT ones, are counted for
-// all.
+// slots of the aligned-tile instantiations are counted for all.
 template <typename T, int BX, int BY>
 constexpr size_t stage_static_lds() {
   using TL = Tile<BX, BY>;
   return sizeof(T) * (2 * (4 * TL::LH * TL::LW + 5 * BY * (BX + 4) + 5 * (BY + 4) * BX) +
-                      (sizeof(T) == 4 ? 1 : 26 * TL::NCOL) + 4 * (TL::NY2 + TL::NX2)) +
+                      4 * (TL::NY2 + TL::NX2)) +
          8 * kNQ * TL::NOWN;
 }
 
-// Occupancy target of the FP64 AT instantiations: no more waves per SIMD than their static LDS
-// (the LDS window) leaves room for, so that they keep the registers of that occupancy.
+// Occupancy target of the FP64 AT instantiations.  A workgroup of at most 4 waves targets one wave
+// per SIMD, so that the z window, the AT state and the gradients fit VGPRs and AGPRs without
+// scratch.  Larger workgroups take no more waves per SIMD than their static LDS leaves room for, so
+// that they keep the registers of that occupancy.
 template <typename T, int BX, int BY>
 constexpr int fp64_at_cap(int m) {
   constexpr int nw = Tile<BX, BY>::NT / 64;
   constexpr int wgs = (int)(kLdsBytes / stage_static_lds<T, BX, BY>());
   constexpr int cap = (wgs * nw + 3) / 4 < 1 ? 1 : (wgs * nw + 3) / 4;
-  return sizeof(T) == 4 || m <= cap ? m : cap;
+  return sizeof(T) == 4 ? m : nw <= 4 ? 1 : m <= cap ? m : cap;
 }
 
 template <typename T, int BX, int BY, int MINW>
