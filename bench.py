@@ -397,7 +397,7 @@ def field_rel_l2(a, b):
 def order6_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K):
     """The sixth-order AT scheme ((1,6) rows, 4-level extrapolation) on the same 512^3 field, FP32,
     unforced (decaying), CAA c_r = 4: timed window, then a kernel-event window for the roofline of
-    its two launches per stage."""
+    its two launches per stage and its extrapolated face values (one launch per delayed step)."""
     total = Wm + 2 * K + 2
     cfg = atns.Config(n=(n,) * 3, p=(pe,) * 3, dt=dt, mu_ref=mu, max_delay=3, precision="fp32", order=6)
     sim = atns.Sim(cfg)
@@ -409,7 +409,7 @@ def order6_leg(torch, atns, W, traffic, n, pe, q, dt, mu, Wm, K):
     sim.close()
     torch.cuda.empty_cache()
     pd = sum(1 for s in range(Wm + K, Wm + 2 * K) if s >= 4 and s % 4) / K
-    rf = roofline(kt, n, pe, 4, pd, K, kernels=("k6_gradflux", "k6_divupdate"), order=6)
+    rf = roofline(kt, n, pe, 4, pd, K, kernels=("k6_gradflux", "k6_divupdate", "k6_ghosts"), order=6)
     rf["traffic"] = measured_traffic(f"k6_stage_{n}_pe{pe}_fp32", "stage6.hip")
     return {"value": n ** 3 * K / (ms * 1e-3), "unit": "grid-pt-steps/s", "ms_per_step": ms / K, "steps": K,
             "kernels_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items()}, "roofline": rf,

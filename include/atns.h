@@ -226,7 +226,7 @@ ATNS_API int at_get_stage_tuning(at_sim* sim, int32_t* tile_sync, int32_t* zchun
  * recorded on the handle's stream; at_kernel_timing synchronises the stream and returns, for kernel
  * `kernel` (0 .. AT_N_KERNELS-1, named by at_kernel_name), the summed event time in ms and the
  * number of launches since timing was enabled.  Errors: AT_E_INVAL, AT_E_HIP. */
-#define AT_N_KERNELS 11
+#define AT_N_KERNELS 12
 ATNS_API int at_set_kernel_timing(at_sim* sim, int32_t enable);
 ATNS_API int at_kernel_timing(at_sim* sim, int32_t kernel, double* total_ms, int64_t* launches);
 ATNS_API const char* at_kernel_name(int32_t kernel);

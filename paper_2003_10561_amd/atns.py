@@ -30,7 +30,7 @@ EXPORTED = ["at_version", "at_last_error", "at_workspace_bytes", "at_create", "a
             "at_batch_graph_stats", "at_batch_destroy", "at_serve", "at_field_stats_noalloc",
             "at_diag_workspace_bytes", "at_field_diagnostics"]
 N_TILES = 7
-N_KERNELS = 11
+N_KERNELS = 12
 
 
 class AtError(RuntimeError):

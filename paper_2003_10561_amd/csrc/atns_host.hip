@@ -119,8 +119,9 @@ Layout make_layout(const at_config* c, const Geom& g) {
   L.q[1] = take(kNQ * N * w);
   L.dq = take(kNQ * N * w);
   L.ring = take((size_t)g.R * g.ring_slot * w);
-  // the AT sums of the three stages of a step (fourth order); the flux buffer (sixth order)
-  L.gv = take(c->order == 4 && c->form == 0 ? (size_t)3 * g.ring_slot * w : 0);
+  // per stage of a step, in ring-slot layout: the AT sums (fourth order) or the extrapolated face
+  // values (sixth order); the flux buffer (sixth order)
+  L.gv = take(c->form == 0 ? (size_t)3 * g.ring_slot * w : 0);
   L.flux = take(c->order == 6 ? (size_t)3 * kNQ * N * w : 0);
   L.grad = take(c->form == 1 ? (size_t)kNGrad * N * w : 0);
   // smallest tile (16 x 4) and smallest z chunk (4) bound the workgroup count of any stage launch
@@ -281,6 +282,7 @@ Stage6Args<T> base6(at_sim* s) {
   a.dq = (T*)(s->ws + s->L.dq);
   a.flux = (T*)(s->ws + s->L.flux);
   a.ring = (T*)(s->ws + s->L.ring);
+  a.gv = (T*)(s->ws + s->L.gv);
   a.tot_part = (double*)(s->ws + s->L.tot_part);
   tile6_of(s->g, &a.bx, &a.by);
   a.delays = s->d_sched ? s->d_sched + (size_t)s->step * s->g.ntiles * 6 : s->d_zero;
@@ -301,6 +303,20 @@ hipError_t launch6_hooked(at_sim* s, const Stage6Args<T>& a, bool div) {
   if (s->timer) s->timer->before(kK6Div, s->stream);
   e = launch_stage6<T>(a, false, s->stream);
   if (s->timer) s->timer->after(kK6Div, s->stream);
+  return e;
+}
+
+// The sixth-order extrapolated face values of the current step for its nst stages (c_s = kRkC[st],
+// or 0 for one Adams-Bashforth or RHS stage), once per step that reads delayed levels.
+template <typename T>
+hipError_t launch_ghosts6_hooked(at_sim* s, int nst) {
+  if (!s->d_sched || !s->step_delayed[(size_t)s->step]) return hipSuccess;
+  Stage6Args<T> a = base6<T>(s);
+  a.nst = nst;
+  for (int st = 0; st < 3; ++st) a.cs3[st] = nst == 3 ? (T)kRkC[st] : T(0);
+  if (s->timer) s->timer->before(kK6Ghost, s->stream);
+  hipError_t e = launch_ghosts6<T>(a, s->stream);
+  if (s->timer) s->timer->after(kK6Ghost, s->stream);
   return e;
 }
 
@@ -417,8 +433,10 @@ template <typename T>
 int do_steps6(at_sim* s, int nsteps) {
   if (nsteps > 0) s->tot_used = std::max(s->tot_used, blocks6(s->g));
   for (int it = 0; it < nsteps; ++it) {
+    HIP_TRY(launch_ghosts6_hooked<T>(s, 3));
     for (int st = 0; st < 3; ++st) {
       Stage6Args<T> a = base6<T>(s);
+      a.gv += (size_t)st * s->g.ring_slot;
       a.cs = (T)kRkC[st];
       a.rk_a = (T)kRkA[st];
       a.rk_b = (T)kRkB[st];
@@ -506,6 +524,7 @@ int do_ab2_steps(at_sim* s, int nsteps) {
   if (s->g.order == 6) {
     if (nsteps > 0) s->tot_used = std::max(s->tot_used, blocks6(s->g));
     for (int it = 0; it < nsteps; ++it) {
+      HIP_TRY(launch_ghosts6_hooked<T>(s, 1));
       Stage6Args<T> a = base6<T>(s);
       a.rk_b = s->ab2_prev ? T(1.5) : T(1);
       a.c_prev = s->ab2_prev ? T(-0.5) : T(0);
@@ -558,6 +577,7 @@ int do_rhs(at_sim* s, void* out) {
     return AT_OK;
   }
   if (s->g.order == 6) {
+    HIP_TRY(launch_ghosts6_hooked<T>(s, 1));
     Stage6Args<T> a = base6<T>(s);
     a.mode = kModeRhsH;
     a.rhs_out = (T*)out;

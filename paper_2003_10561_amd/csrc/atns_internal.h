@@ -144,7 +144,7 @@ constexpr int kModeStepH = 0, kModeRhsH = 1, kModePublishH = 2;
 // Kernel identities for timing (names in kernel_name()).
 enum KernelId {
   kKStage = 0, kKRhs = 1, kKPublish = 2, kKForce = 3, kKStats = 4, kKGhost = 5, kK6Grad = 6, kK6Div = 7,
-  kKPPublish = 8, kKPGrad = 9, kKPRhs = 10, kKCount = 11
+  kKPPublish = 8, kKPGrad = 9, kKPRhs = 10, kK6Ghost = 11, kKCount = 12
 };
 
 // The paper's own discretisation (stagep.hip, form 1): publication of the conserved variables,
@@ -182,12 +182,15 @@ struct Stage6Args {
   T* dq;
   T* flux;            // [3][5][N]
   T* ring;
+  T* gv;              // extrapolated values behind the faces: one ring slot per stage of a step
   T* rhs_out;
   const int8_t* delays;
   double* tot_part;
   int bx, by;
   int step_mod_r, publish, store_dq, mode;
   T cs, rk_a, rk_b, dt, c_prev;
+  T cs3[3];           // the ghost pass: c_s of each of its nst stages
+  int nst;
   double vol;
 };
 void tile6_of(const Geom& g, int* bx, int* by);
@@ -195,6 +198,9 @@ int64_t blocks6(const Geom& g);
 // gradflux: the gradient / flux launch; otherwise the divergence / update launch
 template <typename T>
 hipError_t launch_stage6(const Stage6Args<T>& s, bool gradflux, hipStream_t stream);
+// the extrapolated face values of nst stages (c_s in cs3) into gv, gv + ring_slot, ...
+template <typename T>
+hipError_t launch_ghosts6(const Stage6Args<T>& s, hipStream_t stream);
 const char* kernel_name(int id);
 
 // Optional event bracketing of each launch (host side implements it).

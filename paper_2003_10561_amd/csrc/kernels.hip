@@ -271,7 +271,7 @@ int64_t stats_blocks(const Geom& g) { return update_blocks(g); }
 const char* kernel_name(int id) {
   static const char* names[kKCount] = {"k_stage", "k_stage(rhs)", "k_stage(publish)", "k_force_table",
                                        "k_stats", "k_at_sums", "k6_gradflux", "k6_divupdate",
-                                       "kp_publish", "kp_grad", "kp_rhs"};
+                                       "kp_publish", "kp_grad", "kp_rhs", "k6_ghosts"};
   return (id >= 0 && id < kKCount) ? names[id] : "";
 }
 

@@ -33,6 +33,8 @@ struct A6 {
   T* dq;
   T* flux;           // [3][5][N]: F_d of conserved component c at [(d 5 + c) N + i]
   T* ring;
+  T* gv;             // extrapolated values behind the faces, ring-slot layout: this stage's (stage
+                     // kernels), or the first of nst consecutive ones (k6_ghosts)
   T* rhs_out;
   const int8_t* delays;  // [ntiles][6] for this step
   double* tot_part;
@@ -43,6 +45,8 @@ struct A6 {
   int gbx, gby;      // workgroups along x and y
   int R, step_mod_r, publish, store_dq, mode;
   T cs;              // c_s of this stage
+  T cs3[3];          // k6_ghosts: c_s of each stage it forms
+  int nst;
   T i60x, i60y, i60z, gas_r, inv_cv, cp_over_pr, mu_ref, inv_tref, mu_exp;
   T rk_a, rk_b, dt, c_prev;
   double vol;
@@ -120,32 +124,94 @@ __device__ __forceinline__ uint32_t slab6(const A6<T>& a, int d) {
 }
 
 // Extrapolated value of ring component `comp` (0..3 u, v, w, T; 4..8 face-normal flux) at ring
-// offset `off` of direction d, for delay k at this stage.
+// offset `off` of direction d, as the PE reading it across its delayed face sees it at this stage
+// (formed by k6_ghosts for that reader's delay).
 template <typename T>
-__device__ __forceinline__ T ghost6(const A6<T>& a, int d, int comp, uint32_t off, int k) {
-  T w[4];
-  weights6<T>(T(k) + a.cs, w);
-  int s = a.step_mod_r - k;
-  s += s < 0 ? a.R : 0;
-  T v = T(0);
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const T* r = a.ring + (uint32_t)s * a.rslot;
-    v += w[l] * r[off + (uint32_t)comp * slab6(a, d)];
-    s = s == 0 ? a.R - 1 : s - 1;
-  }
-  return v;
+__device__ __forceinline__ T ghost6(const A6<T>& a, int d, int comp, uint32_t off) {
+  return a.gv[off + (uint32_t)comp * slab6(a, d)];
 }
 
-// Workgroup decode: tile (bkx, bky), z-PE bkz.
+// Extrapolated values behind the PE faces for the stages of one step (Sec. 2.1, Eq. at; Appendix
+// B, (1,6) rows), one thread per element e of a ring slot.  Element e (direction d, component c,
+// layer jp = 6 t + j of PE t along d) is read across a face by one PE only, its neighbour on the
+// layer's side: PE t - 1 across its upper face for the lower layers (j < 3), PE t + 1 across its
+// lower face for the upper ones.  With that reader's delay k >= 1, stage s gets the cubic
+// extrapolation to kappa = k + c_s of levels n - k .. n - k - 3, written at e of its slot-sized
+// buffer; elements whose reader is not delayed are left alone (no stage reads them).  The four
+// levels are read once for all the stages, coalesced.
 template <typename T>
-__device__ __forceinline__ void decode6(const A6<T>& a, int& bkx, int& bky, int& bkz) {
-  const int b = (int)blockIdx.x;
+__global__ __launch_bounds__(256) void k6_ghosts(A6<T> a) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= a.rslot) return;
+  const int d = e < a.rdir1 ? 0 : (e < a.rdir2 ? 1 : 2);
+  const uint32_t pos = (e - (d == 0 ? 0u : (d == 1 ? a.rdir1 : a.rdir2))) % slab6(a, d);
+  int jp, tx, ty, tz;
+  if (d == 0) {  // pos = (z ny + y) 6 px + jp
+    const uint32_t w6 = 6u * (uint32_t)a.px, zy = pos / w6;
+    jp = (int)(pos - zy * w6);
+    ty = (int)(zy % (uint32_t)a.ny) / a.ey;
+    tz = (int)(zy / (uint32_t)a.ny) / a.ez;
+    tx = jp / 6;
+  } else if (d == 1) {  // pos = (z 6 py + jp) nx + x
+    const uint32_t r = pos / (uint32_t)a.nx, h6 = 6u * (uint32_t)a.py;
+    tx = (int)(pos - r * (uint32_t)a.nx) / a.ex;
+    jp = (int)(r % h6);
+    tz = (int)(r / h6) / a.ez;
+    ty = jp / 6;
+  } else {  // pos = (jp ny + y) nx + x
+    const uint32_t r = pos / (uint32_t)a.nx;
+    tx = (int)(pos - r * (uint32_t)a.nx) / a.ex;
+    ty = (int)(r % (uint32_t)a.ny) / a.ey;
+    jp = (int)(r / (uint32_t)a.ny);
+    tz = jp / 6;
+  }
+  const bool low = jp - 6 * (jp / 6) < kM6;
+  const int np = d == 0 ? a.px : (d == 1 ? a.py : a.pz);
+  int t = jp / 6;
+  t = low ? (t == 0 ? np - 1 : t - 1) : (t == np - 1 ? 0 : t + 1);
+  tx = d == 0 ? t : tx;
+  ty = d == 1 ? t : ty;
+  tz = d == 2 ? t : tz;
+  const int k = a.delays[((tz * a.py + ty) * a.px + tx) * 6 + 2 * d + (low ? 1 : 0)];
+  if (k <= 0) return;
+  T lev[4];
+  int s = a.step_mod_r - k;
+  s += s < 0 ? a.R : 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    lev[l] = a.ring[(uint32_t)s * a.rslot + e];
+    s = s == 0 ? a.R - 1 : s - 1;
+  }
+  for (int st = 0; st < a.nst; ++st) {
+    T w[4];
+    weights6<T>(T(k) + a.cs3[st], w);
+    T v = T(0);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) v += w[l] * lev[l];
+    __builtin_nontemporal_store(v, a.gv + (uint32_t)st * a.rslot + e);
+  }
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (dispatch index w to XCD w mod 8), each with its own
+// L2.  Logical workgroup xcd_major(w, nb) gives each XCD a contiguous range of tiles, so the tiles
+// whose 3-point halos overlap run on the same L2 (a bijection of [0, nb)).
+constexpr uint32_t kNumXcd = 8;
+__device__ __forceinline__ uint32_t xcd_major(uint32_t w, uint32_t nb) {
+  const uint32_t c = w % kNumXcd, i = w / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
+  return c * q + min(c, r) + i;
+}
+
+// Workgroup decode: tile (bkx, bky), z-PE bkz of the logical workgroup, which is returned.
+template <typename T>
+__device__ __forceinline__ uint32_t decode6(const A6<T>& a, int& bkx, int& bky, int& bkz) {
+  const uint32_t L = xcd_major(blockIdx.x, gridDim.x);
+  const int b = (int)L;
   const int gxy = a.gbx * a.gby;
   bkz = b / gxy;
   const int r = b - bkz * gxy;
   bky = r / a.gbx;
   bkx = r - bky * a.gbx;
+  return L;
 }
 
 // Primitives u, v, w, T at global (x, y, z) as the workgroup's PE sees them: across its face f
@@ -160,10 +226,10 @@ __device__ __forceinline__ void seen_prims(const A6<T>& a, int x, int y, int z, 
   if (crossed >= 0 && kf[crossed] > 0) {
     const int d = crossed >> 1;
     const uint32_t o = ring_off6(a, d, x, y, z);
-    u = ghost6(a, d, 0, o, kf[crossed]);
-    v = ghost6(a, d, 1, o, kf[crossed]);
-    w = ghost6(a, d, 2, o, kf[crossed]);
-    t = ghost6(a, d, 3, o, kf[crossed]);
+    u = ghost6(a, d, 0, o);
+    v = ghost6(a, d, 1, o);
+    w = ghost6(a, d, 2, o);
+    t = ghost6(a, d, 3, o);
   } else {
     load_prims(a, ((uint32_t)z * a.ny + y) * (uint32_t)a.nx + x, u, v, w, t);
   }
@@ -176,7 +242,7 @@ __device__ __forceinline__ T seen_flux(const A6<T>& a, int d, int c, int x, int 
   x = wrapi(x, a.nx);
   y = wrapi(y, a.ny);
   z = wrapi(z, a.nz);
-  if (crossed >= 0 && kf[crossed] > 0) return ghost6(a, d, 4 + c, ring_off6(a, d, x, y, z), kf[crossed]);
+  if (crossed >= 0 && kf[crossed] > 0) return ghost6(a, d, 4 + c, ring_off6(a, d, x, y, z));
   return a.flux[(uint32_t)(d * 5 + c) * a.N + ((uint32_t)z * a.ny + y) * (uint32_t)a.nx + x];
 }
 
@@ -318,7 +384,7 @@ __global__ __launch_bounds__(256) void k6_divupdate(A6<T> a) {
   T* s_fy = s_fx + 5 * BY * LWX;          // [5][LHY][BX]
   double* s_red = reinterpret_cast<double*>(s_fy + 5 * LHY * BX + ((5 * LHY * BX + 5 * BY * LWX) & 1));
   int bkx, bky, bkz;
-  decode6(a, bkx, bky, bkz);
+  const uint32_t blk = decode6(a, bkx, bky, bkz);  // slot of the FP64 block totals
   const int tid = threadIdx.x, lx = tid % BX, ly = tid / BX, NT = BX * BY;
   const int x0 = bkx * BX, y0 = bky * BY, z0 = bkz * a.ez, z1 = z0 + a.ez;
   const int tx = x0 / a.ex, ty = y0 / a.ey, tz = bkz;
@@ -413,7 +479,7 @@ __global__ __launch_bounds__(256) void k6_divupdate(A6<T> a) {
     }
     if (tid == 0) {
       const double scale = a.c_prev != T(0) ? 1.0 : (double)a.rk_b;
-      a.tot_part[(uint32_t)blockIdx.x * kNQ + c] += scale * s_red[0] * a.vol;
+      a.tot_part[blk * kNQ + c] += scale * s_red[0] * a.vol;
     }
     __syncthreads();
   }
@@ -428,6 +494,7 @@ A6<T> pack6(const Stage6Args<T>& s) {
   a.dq = s.dq;
   a.flux = s.flux;
   a.ring = s.ring;
+  a.gv = s.gv;
   a.rhs_out = s.rhs_out;
   a.delays = s.delays;
   a.tot_part = s.tot_part;
@@ -458,6 +525,8 @@ A6<T> pack6(const Stage6Args<T>& s) {
   a.store_dq = s.store_dq;
   a.mode = s.mode;
   a.cs = s.cs;
+  for (int st = 0; st < 3; ++st) a.cs3[st] = s.cs3[st];
+  a.nst = s.nst;
   for (int d = 0; d < 3; ++d) (d == 0 ? a.i60x : d == 1 ? a.i60y : a.i60z) = s.i60h[d];
   a.gas_r = s.cf.gas_r;
   a.inv_cv = s.cf.inv_cv;
@@ -508,5 +577,17 @@ hipError_t launch_stage6(const Stage6Args<T>& s, bool gradflux, hipStream_t stre
 
 template hipError_t launch_stage6<float>(const Stage6Args<float>&, bool, hipStream_t);
 template hipError_t launch_stage6<double>(const Stage6Args<double>&, bool, hipStream_t);
+
+template <typename T>
+hipError_t launch_ghosts6(const Stage6Args<T>& s, hipStream_t stream) {
+  if (s.nst < 1 || s.nst > 3 || !s.gv) return hipErrorInvalidValue;
+  const A6<T> a = pack6<T>(s);
+  const dim3 grid((unsigned)((a.rslot + 255u) / 256u)), block(256);
+  hipLaunchKernelGGL(k6_ghosts<T>, grid, block, 0, stream, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_ghosts6<float>(const Stage6Args<float>&, hipStream_t);
+template hipError_t launch_ghosts6<double>(const Stage6Args<double>&, hipStream_t);
 
 }  // namespace atns

@@ -60,12 +60,13 @@ def test_workspace_bytes_formula(lib):
 
 
 def test_workspace_bytes_formula_order6(lib):
-    """Sixth order: three face layers per side (phi = 6 (1/ex + 1/ey + 1/ez)), a ring of L + 4 levels
-    and the 15-component flux buffer instead of the AT-sum buffers."""
+    """Sixth order: three face layers per side (phi = 6 (1/ex + 1/ey + 1/ez)), a ring of L + 4 levels,
+    three ring-slot buffers of extrapolated face values (one per stage) and the 15-component flux
+    buffer."""
     b64 = atns.workspace_bytes(cfg(order=6))
     N = 32 ** 3
     phi = 6 * (1 / 16 + 1 / 16 + 1 / 32)
-    ring = (3 + 4) * 9 * phi * N
+    ring = (3 + 4 + 3) * 9 * phi * N
     need = 8 * (5 + 5 + 5 + 15) * N + 8 * ring
     assert need <= b64 <= 1.1 * need
 
