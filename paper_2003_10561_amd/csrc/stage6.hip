@@ -276,6 +276,10 @@ __global__ __launch_bounds__(256) void k6_gradflux(A6<T> a) {
   const int nhalo = 2 * kM6 * (BX + BY);
   T* rb = a.ring + (uint32_t)a.step_mod_r * a.rslot;
   for (int zc = z0; zc < z1; ++zc) {
+    // density and energy of this plane, issued first so that they arrive in the round trip of the
+    // window and halo fetches (a wave's loads complete in order)
+    const uint32_t i = ((uint32_t)zc * a.ny + Y) * (uint32_t)a.nx + X;
+    const T rho = a.q[i], E = a.q[4 * a.N + i];
     {
       const int z = zc + 3;
       seen_prims(a, X, Y, z, zcross(z), kf, win[0][6], win[1][6], win[2][6], win[3][6]);
@@ -316,8 +320,6 @@ __global__ __launch_bounds__(256) void k6_gradflux(A6<T> a) {
       G[base + 1] = gy;
       G[base + 2] = gz;
     }
-    const uint32_t i = ((uint32_t)zc * a.ny + Y) * (uint32_t)a.nx + X;
-    const T rho = a.q[i], E = a.q[4 * a.N + i];
     const T u = win[0][3], v = win[1][3], w = win[2][3], t = win[3][3];
     const T mu = visc6<T>(a, t);
     const T kt = mu * a.cp_over_pr;
@@ -406,13 +408,22 @@ __global__ __launch_bounds__(256) void k6_divupdate(A6<T> a) {
   }
   double tsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int nhx = 2 * kM6 * BY, nhy = 2 * kM6 * BX;
+  const bool upd = a.mode != kModeRhsH, keep = a.rk_a != T(0) || a.c_prev != T(0);
   for (int zc = z0; zc < z1; ++zc) {
+    const uint32_t i = ((uint32_t)zc * a.ny + Y) * (uint32_t)a.nx + X;
+    // this plane's state and RK register, issued before the fluxes so that they arrive in the
+    // same round trip (a wave's loads complete in order)
+    T qv[5], prev[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      qv[c] = upd ? a.q[(uint32_t)c * a.N + i] : T(0);
+      prev[c] = upd && keep ? __builtin_nontemporal_load(a.dq + (uint32_t)c * a.N + i) : T(0);
+    }
     {
       const int z = zc + 3;
 #pragma unroll
       for (int c = 0; c < 5; ++c) fz[c][6] = seen_flux(a, 2, c, X, Y, z, zcross(z), kf);
     }
-    const uint32_t i = ((uint32_t)zc * a.ny + Y) * (uint32_t)a.nx + X;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       s_fx[(c * BY + ly) * LWX + lx + kM6] = a.flux[(uint32_t)c * a.N + i];
@@ -452,13 +463,10 @@ __global__ __launch_bounds__(256) void k6_divupdate(A6<T> a) {
     } else {
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        const T qv = a.q[(uint32_t)c * a.N + i];
-        const T prev = (a.rk_a != T(0) || a.c_prev != T(0)) ? __builtin_nontemporal_load(a.dq + (uint32_t)c * a.N + i)
-                                                             : T(0);
-        const T d = a.rk_a * prev + a.dt * rhs[c];
-        const T inc = a.rk_b * d + a.c_prev * prev;
+        const T d = a.rk_a * prev[c] + a.dt * rhs[c];
+        const T inc = a.rk_b * d + a.c_prev * prev[c];
         if (a.store_dq) __builtin_nontemporal_store(d, a.dq + (uint32_t)c * a.N + i);
-        __builtin_nontemporal_store(qv + inc, a.q_out + (uint32_t)c * a.N + i);
+        __builtin_nontemporal_store(qv[c] + inc, a.q_out + (uint32_t)c * a.N + i);
         tsum[c] += a.c_prev != T(0) ? (double)inc : (double)d;
       }
     }
